@@ -1,0 +1,312 @@
+"""FP64 CPU oracle for the Hypercube-Givens transform (HyGT).
+
+TEST INFRASTRUCTURE ONLY. This module is the plain, slow, obviously correct
+statement of what the GPU library computes. It exists so that the tests, the
+smoke check and the benchmark's CPU-baseline leg can compare the HIP path
+against it. The product path never imports it, and it imports nothing from the
+product: the two share no kernels, helpers, tables or constants.
+
+Source: Said, Zhao, Karczewicz, Egilmez, Seregin, Chen, "Highly Efficient
+Non-Separable Transforms for Next Generation Video Coding" (arXiv 2505.21728).
+
+Conventions fixed here (the paper's figures are not available; each reading is
+listed with its justification in the design notes):
+
+* A block is a vector of N = 2**d residuals (Sec. II, signal-adaptive model).
+* The Givens rotation G(m, n, theta) is the identity except
+  G[m,m] = G[n,n] = cos(theta), G[m,n] = +sin(theta), G[n,m] = -sin(theta)
+  (Sec. IV, element definition). Applied as y = G x this is
+  y_m = cos*x_m + sin*x_n,  y_n = -sin*x_m + cos*x_n.
+* Pass k of a round pairs every index with its neighbour along hypercube
+  dimension k, i.e. (i, i XOR 2**k) (Sec. IV, Fig. 3 caption and Fig. 5).
+  Angle j of pass k belongs to pair number j in the enumeration of Fig. 5:
+  m = j with a zero bit inserted at position k, n = m + 2**k.
+* A round applies passes k = 0, 1, ..., d-1; the transform applies rounds
+  0..R-1; the first pass applied is F_1 of eq. (5).
+* Angle table layout: angles[class, round, pass, j], radians.
+* The inverse applies the passes in reverse order with negated angles
+  (eq. (6), eq. (9), Sec. IV).
+* Class indices are 0-based.
+
+Every function states the passage it follows. Parity pins for each function
+live in tests/test_oracle.py.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "pair_indices",
+    "forward",
+    "inverse",
+    "givens_matrix",
+    "parallel_givens_matrix",
+    "transform_matrix_from_passes",
+    "transform_matrix_from_columns",
+    "num_parameters",
+    "klt_parameters",
+    "memory_usage_ratio",
+    "round_to_bf16",
+    "dense_transform",
+    "rel_l2_per_block",
+    "rel_l2_global",
+]
+
+
+# ---------------------------------------------------------------------------
+# Hypercube index pairs (Sec. IV, Fig. 5)
+# ---------------------------------------------------------------------------
+
+def pair_indices(d: int, k: int) -> tuple[np.ndarray, np.ndarray]:
+    """Index vectors (m, n) of pass k on a d-dimensional hypercube.
+
+    Sec. IV: the passes of a round take the hypercube edges one dimension at a
+    time. For pair number j (0 <= j < N/2) the lower index m is j with a zero
+    bit inserted at bit position k, and n = m + 2**k (the same pairs Fig. 5
+    enumerates). The pairs cover {0, ..., N-1} exactly once (eq. (7)).
+    """
+    if not (1 <= d) or not (0 <= k < d):
+        raise ValueError("need d >= 1 and 0 <= k < d")
+    half = 1 << (d - 1)
+    m = np.empty(half, dtype=np.int64)
+    n = np.empty(half, dtype=np.int64)
+    low_mask = (1 << k) - 1
+    for j in range(half):
+        high = j >> k          # bits of j at and above position k
+        low = j & low_mask     # bits of j below position k
+        mj = (high << (k + 1)) | low
+        m[j] = mj
+        n[j] = mj + (1 << k)
+    return m, n
+
+
+# ---------------------------------------------------------------------------
+# Batched transform (eq. (5), (6), (8), (9); Sec. IV)
+# ---------------------------------------------------------------------------
+
+def _check(x: np.ndarray, cls: np.ndarray | None, angles: np.ndarray):
+    x = np.asarray(x, dtype=np.float64)
+    angles = np.asarray(angles, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("x must be [nblocks, N]")
+    if angles.ndim != 4:
+        raise ValueError("angles must be [C, R, d, N/2]")
+    nclasses, rounds, d, half = angles.shape
+    n_elems = 1 << d
+    if x.shape[1] != n_elems or half != n_elems // 2:
+        raise ValueError("shape mismatch between x and angles")
+    if cls is None:
+        if nclasses != 1:
+            raise ValueError("cls may be omitted only when there is one class")
+        cls = np.zeros(x.shape[0], dtype=np.int64)
+    cls = np.asarray(cls, dtype=np.int64)
+    if cls.shape != (x.shape[0],):
+        raise ValueError("cls must be [nblocks]")
+    if cls.size and (cls.min() < 0 or cls.max() >= nclasses):
+        raise ValueError("class index out of range")
+    return x, cls, angles, rounds, d
+
+
+def forward(x, cls, angles) -> np.ndarray:
+    """y[b] = T_{cls[b]} x[b] in FP64.
+
+    T_c = F_P ... F_1 (eq. (5)), F for round r and pass k being the
+    parallel-Givens matrix G(m, n, theta_{c,r,k}) of eq. (8) with the
+    hypercube pairs of pass k. Rounds go 0..R-1, passes 0..d-1 inside each
+    round (Sec. IV). Each pair is rotated with the element definition of G:
+    y_m = cos*x_m + sin*x_n, y_n = -sin*x_m + cos*x_n.
+    """
+    x, cls, angles, rounds, d = _check(x, cls, angles)
+    v = x.copy()
+    for r in range(rounds):
+        for k in range(d):
+            m, n = pair_indices(d, k)
+            theta = angles[cls, r, k, :]          # [B, N/2]
+            c = np.cos(theta)
+            s = np.sin(theta)
+            xm = v[:, m].copy()
+            xn = v[:, n].copy()
+            v[:, m] = c * xm + s * xn
+            v[:, n] = -s * xm + c * xn
+    return v
+
+
+def inverse(y, cls, angles) -> np.ndarray:
+    """z[b] = T_{cls[b]}^{-1} y[b] in FP64.
+
+    eq. (6): the inverse is the product of the inverse passes in reverse
+    order. eq. (9): the inverse of a parallel-Givens pass is the same pass with
+    negated angles. So rounds run R-1..0, passes d-1..0, and each pair gets
+    y_m = cos*x_m - sin*x_n, y_n = sin*x_m + cos*x_n.
+    """
+    y, cls, angles, rounds, d = _check(y, cls, angles)
+    v = y.copy()
+    for r in reversed(range(rounds)):
+        for k in reversed(range(d)):
+            m, n = pair_indices(d, k)
+            theta = -angles[cls, r, k, :]
+            c = np.cos(theta)
+            s = np.sin(theta)
+            xm = v[:, m].copy()
+            xn = v[:, n].copy()
+            v[:, m] = c * xm + s * xn
+            v[:, n] = -s * xm + c * xn
+    return v
+
+
+# ---------------------------------------------------------------------------
+# Dense matrices built from the definitions (for tiny N)
+# ---------------------------------------------------------------------------
+
+def givens_matrix(n_elems: int, m: int, n: int, theta: float) -> np.ndarray:
+    """G(m, n, theta) written out element by element (Sec. IV definition)."""
+    g = np.zeros((n_elems, n_elems), dtype=np.float64)
+    for i in range(n_elems):
+        for j in range(n_elems):
+            if i == j and (i == m or i == n):
+                g[i, j] = math.cos(theta)
+            elif i == m and j == n:
+                g[i, j] = math.sin(theta)
+            elif i == n and j == m:
+                g[i, j] = -math.sin(theta)
+            elif i == j:
+                g[i, j] = 1.0
+    return g
+
+
+def parallel_givens_matrix(d: int, k: int, thetas) -> np.ndarray:
+    """G(m, n, theta) of eq. (8): the product of the N/2 rotations of pass k."""
+    n_elems = 1 << d
+    m, n = pair_indices(d, k)
+    out = np.eye(n_elems)
+    for j in range(n_elems // 2):
+        out = out @ givens_matrix(n_elems, int(m[j]), int(n[j]), float(thetas[j]))
+    return out
+
+
+def transform_matrix_from_passes(angles_c) -> np.ndarray:
+    """T = F_P ... F_2 F_1 (eq. (5)) as a product of dense pass matrices.
+
+    angles_c is one class's table [R, d, N/2]; F_1 is round 0, pass 0.
+    """
+    angles_c = np.asarray(angles_c, dtype=np.float64)
+    rounds, d, _ = angles_c.shape
+    t = np.eye(1 << d)
+    for r in range(rounds):
+        for k in range(d):
+            t = parallel_givens_matrix(d, k, angles_c[r, k]) @ t
+    return t
+
+
+def transform_matrix_from_columns(angles_c) -> np.ndarray:
+    """T built column by column: column i is forward(e_i)."""
+    angles_c = np.asarray(angles_c, dtype=np.float64)
+    n_elems = 1 << angles_c.shape[1]
+    eye = np.eye(n_elems)
+    cols = forward(eye, np.zeros(n_elems, dtype=np.int64), angles_c[None])
+    return cols.T
+
+
+# ---------------------------------------------------------------------------
+# Parameter counts and Table II memory ratios (Sec. IV, Sec. VI)
+# ---------------------------------------------------------------------------
+
+def num_parameters(n_elems: int, rounds: int) -> int:
+    """Angles in one HyGT: R * N * log2(N) / 2 (Sec. IV)."""
+    d = int(round(math.log2(n_elems)))
+    if 1 << d != n_elems:
+        raise ValueError("N must be a power of two")
+    return rounds * n_elems * d // 2
+
+
+def klt_parameters(n_elems: int) -> int:
+    """Entries of one dense N x N KLT matrix (eq. (3))."""
+    return n_elems * n_elems
+
+
+def memory_usage_ratio(scheme_4x4: str, scheme_8x8: str, which: str) -> float:
+    """Memory used by KLTs divided by memory used by the scheme (Table II).
+
+    A scheme name is "K" (dense KLT) or "H(R)" (HyGT with R rounds). The same
+    number of transforms is stored for each block size (105 per size), so the
+    ratios depend only on per-transform parameter counts. `which` selects the
+    4x4 set, the 8x8 set or both ("avg", the average row of Table II, taken as
+    the ratio of totals over the two sizes).
+    """
+    def count(name: str, n_elems: int) -> int:
+        if name == "K":
+            return klt_parameters(n_elems)
+        if name.startswith("H(") and name.endswith(")"):
+            return num_parameters(n_elems, int(name[2:-1]))
+        raise ValueError(name)
+
+    klt4, klt8 = klt_parameters(16), klt_parameters(64)
+    s4, s8 = count(scheme_4x4, 16), count(scheme_8x8, 64)
+    if which == "4x4":
+        return klt4 / s4
+    if which == "8x8":
+        return klt8 / s8
+    if which == "avg":
+        return (klt4 + klt8) / (s4 + s8)
+    raise ValueError(which)
+
+
+# ---------------------------------------------------------------------------
+# Dense per-class matrix transform, the KLT-shaped comparison (eq. (3))
+# ---------------------------------------------------------------------------
+
+def round_to_bf16(a) -> np.ndarray:
+    """Round FP32 values to the nearest bfloat16 (ties to even), as FP64.
+
+    bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits
+    of an IEEE binary32. Rounding adds half an ulp of the kept part (plus the
+    kept lowest bit for ties-to-even) before truncation. Inputs must be finite.
+    """
+    a32 = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    bits = a32.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    rounded = (bits + 0x7FFF + lsb) & 0xFFFF0000
+    return rounded.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def dense_transform(x, cls, mats) -> np.ndarray:
+    """y[b] = K_{cls[b]} x[b] (eq. (3)) in FP64 for dense per-class matrices."""
+    x = np.asarray(x, dtype=np.float64)
+    mats = np.asarray(mats, dtype=np.float64)
+    cls = np.asarray(cls, dtype=np.int64)
+    y = np.empty_like(x)
+    for b in range(x.shape[0]):
+        y[b] = mats[cls[b]] @ x[b]
+    return y
+
+
+# ---------------------------------------------------------------------------
+# Comparison metric
+# ---------------------------------------------------------------------------
+
+def rel_l2_per_block(approx, exact) -> np.ndarray:
+    """||approx_b - exact_b||_2 / ||exact_b||_2 per block.
+
+    A block whose exact value is all zeros reports its absolute error norm
+    (which must be exactly zero for a pass).
+    """
+    approx = np.asarray(approx, dtype=np.float64)
+    exact = np.asarray(exact, dtype=np.float64)
+    num = np.sqrt(np.sum((approx - exact) ** 2, axis=1))
+    den = np.sqrt(np.sum(exact ** 2, axis=1))
+    out = num.copy()
+    nz = den > 0
+    out[nz] = num[nz] / den[nz]
+    return out
+
+
+def rel_l2_global(approx, exact) -> float:
+    """||approx - exact||_2 / ||exact||_2 over all blocks concatenated."""
+    approx = np.asarray(approx, dtype=np.float64)
+    exact = np.asarray(exact, dtype=np.float64)
+    den = float(np.sqrt(np.sum(exact ** 2)))
+    num = float(np.sqrt(np.sum((approx - exact) ** 2)))
+    return num / den if den > 0 else num

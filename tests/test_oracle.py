@@ -1,0 +1,373 @@
+"""Pins for the FP64 oracle: what the paper and the mathematics fix.
+
+Every check compares the oracle with something other than itself: values
+worked out by hand from the paper's definitions (tests/golden), closed forms
+(Kronecker products of 2x2 rotations, the Walsh-Hadamard matrix from scipy),
+invariants of orthogonal matrices, and an independent dense construction from
+the element definition of the Givens matrix. The mutation tests at the end
+plant plausible mistakes in a copy of the oracle and check that at least one
+pin fails for each.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import hygt_oracle as orc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _rand_angles(rng, nclasses, rounds, d):
+    return rng.uniform(-math.pi, math.pi, (nclasses, rounds, d, 1 << (d - 1)))
+
+
+# ---------------------------------------------------------------------------
+# Pin functions (also re-run against mutants at the bottom of the file)
+# ---------------------------------------------------------------------------
+
+def pin_fig5_indices(o):
+    """P5: pairs equal Fig. 5's m = j + (j & -k), n = m + k for d = 1..8."""
+    g = _load("fig5_hypercube_d3.json")
+    for i in range(3):
+        m, n = o.pair_indices(3, i)
+        assert list(m) == g["m"][i] and list(n) == g["n"][i]
+    for d in range(1, 9):
+        for i in range(d):
+            k = 1 << i
+            m, n = o.pair_indices(d, i)
+            for j in range(1 << (d - 1)):
+                assert m[j] == j + (j & -k)
+                assert n[j] == m[j] + k
+
+
+def pin_n2_worked(o):
+    """P2: one rotation on N = 2 against hand-worked values (Sec. IV)."""
+    g = _load("givens_n2_worked.json")
+    table = {"pi/4": math.pi / 4, "pi/2": math.pi / 2, "-pi/2": -math.pi / 2,
+             "pi/3": math.pi / 3, "pi": math.pi}
+    for case in g["cases"]:
+        th = table[case["theta"]]
+        y = o.forward(np.array([case["x"]]), None, np.array([[[[th]]]]))
+        np.testing.assert_allclose(y[0], case["y"], rtol=0, atol=1e-14)
+
+
+def pin_zero_angles_identity(o):
+    """P1: all angles zero give the identity, exactly."""
+    rng = np.random.default_rng(10)
+    for d, rounds in [(1, 1), (4, 2), (6, 4)]:
+        x = rng.standard_normal((7, 1 << d))
+        ang = np.zeros((1, rounds, d, 1 << (d - 1)))
+        assert np.array_equal(o.forward(x, None, ang), x)
+        assert np.array_equal(o.inverse(x, None, ang), x)
+
+
+def pin_single_angle_layout(o):
+    """P6: only angle (r, k, j) nonzero gives exactly G(m_j, n_j, theta) of
+    Fig. 5's pair j of pass k, written out as a literal 2x2 block."""
+    d, rounds = 3, 2
+    n_el = 1 << d
+    th = 0.7
+    c, s = math.cos(th), math.sin(th)
+    for r in range(rounds):
+        for k in range(d):
+            kk = 1 << k
+            for j in range(n_el // 2):
+                ang = np.zeros((1, rounds, d, n_el // 2))
+                ang[0, r, k, j] = th
+                t = o.transform_matrix_from_columns(ang[0])
+                mj = j + (j & -kk)
+                nj = mj + kk
+                expect = np.eye(n_el)
+                expect[mj, mj] = c
+                expect[nj, nj] = c
+                expect[mj, nj] = s
+                expect[nj, mj] = -s
+                np.testing.assert_allclose(t, expect, rtol=0, atol=1e-15)
+
+
+def pin_pass_order(o):
+    """P7: pass 0 pair (0,1) angle a, pass 1 pair (0,2) angle b, N = 4.
+
+    eq. (5) applies F_1 first, so T = G(0,2,b) G(0,1,a), written out by hand.
+    Also round order: the same two angles in round 1 pass 0 / round 0 pass 1
+    must give T = G(0,1,a) G(0,2,b)."""
+    a, b = 0.3, -1.1
+    ca, sa, cb, sb = math.cos(a), math.sin(a), math.cos(b), math.sin(b)
+    g01 = np.array([[ca, sa, 0, 0], [-sa, ca, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1.0]])
+    g02 = np.array([[cb, 0, sb, 0], [0, 1, 0, 0], [-sb, 0, cb, 0], [0, 0, 0, 1.0]])
+    ang = np.zeros((1, 1, 2, 2))
+    ang[0, 0, 0, 0] = a
+    ang[0, 0, 1, 0] = b
+    t = o.transform_matrix_from_columns(ang[0])
+    np.testing.assert_allclose(t, g02 @ g01, rtol=0, atol=1e-15)
+    ang2 = np.zeros((1, 2, 2, 2))
+    ang2[0, 1, 0, 0] = a
+    ang2[0, 0, 1, 0] = b
+    t2 = o.transform_matrix_from_columns(ang2[0])
+    np.testing.assert_allclose(t2, g01 @ g02, rtol=0, atol=1e-15)
+
+
+def pin_kronecker(o):
+    """P8: equal angles alpha_{r,k} inside every pass give
+    T = g(sum_r alpha_{r,d-1}) (x) ... (x) g(sum_r alpha_{r,0}),
+    g(phi) = [[cos phi, sin phi], [-sin phi, cos phi]] acting on bit k."""
+    rng = np.random.default_rng(11)
+    for d, rounds in [(1, 3), (3, 3), (4, 2), (5, 1)]:
+        alpha = rng.uniform(-math.pi, math.pi, (rounds, d))
+        ang = np.repeat(alpha[:, :, None], 1 << (d - 1), axis=2)[None]
+        t = o.transform_matrix_from_columns(ang[0])
+        expect = np.ones((1, 1))
+        for k in reversed(range(d)):
+            phi = alpha[:, k].sum()
+            g = np.array([[math.cos(phi), math.sin(phi)], [-math.sin(phi), math.cos(phi)]])
+            expect = np.kron(expect, g)
+        np.testing.assert_allclose(t, expect, rtol=0, atol=1e-13)
+
+
+def pin_walsh_hadamard(o):
+    """P9: one round with every angle pi/4 is diag((-1)^popcount(i)) H_N / sqrt(N)
+    with H_N the Sylvester-ordered Hadamard matrix (scipy.linalg.hadamard)."""
+    for d in range(1, 7):
+        n_el = 1 << d
+        ang = np.full((1, 1, d, n_el // 2), math.pi / 4)
+        t = o.transform_matrix_from_columns(ang[0])
+        signs = np.array([(-1) ** bin(i).count("1") for i in range(n_el)], dtype=np.float64)
+        expect = signs[:, None] * scipy.linalg.hadamard(n_el) / math.sqrt(n_el)
+        np.testing.assert_allclose(t, expect, rtol=0, atol=1e-13)
+
+
+def pin_dense_product(o):
+    """P4: T from unit vectors equals the product of pass matrices built from
+    the element definition of G (eq. (5), eq. (8))."""
+    rng = np.random.default_rng(12)
+    for d, rounds in [(1, 1), (1, 3), (2, 1), (2, 2), (3, 2), (4, 2)]:
+        ang = _rand_angles(rng, 1, rounds, d)[0]
+        np.testing.assert_allclose(o.transform_matrix_from_columns(ang),
+                                   o.transform_matrix_from_passes(ang), rtol=0, atol=1e-13)
+
+
+def pin_orthogonality(o):
+    """P3 and P11: T^T T = I, det T = +1, norms kept, inverse(forward(x)) = x,
+    inverse(e_i) = row i of T."""
+    rng = np.random.default_rng(13)
+    for d, rounds in [(2, 1), (4, 2), (6, 4)]:
+        n_el = 1 << d
+        ang = _rand_angles(rng, 3, rounds, d)
+        for c in range(3):
+            t = o.transform_matrix_from_columns(ang[c])
+            np.testing.assert_allclose(t.T @ t, np.eye(n_el), rtol=0, atol=1e-12)
+            assert abs(np.linalg.det(t) - 1.0) < 1e-10
+            rows = o.inverse(np.eye(n_el), np.full(n_el, c), ang)
+            np.testing.assert_allclose(rows, t, rtol=0, atol=1e-12)
+        x = 50 * rng.standard_normal((40, n_el))
+        cls = rng.integers(0, 3, 40)
+        y = o.forward(x, cls, ang)
+        np.testing.assert_allclose(np.linalg.norm(y, axis=1), np.linalg.norm(x, axis=1), rtol=1e-13)
+        np.testing.assert_allclose(o.inverse(y, cls, ang), x, rtol=0, atol=1e-11)
+
+
+def pin_linearity_and_zero(o):
+    """P10 and P12: zero blocks stay exactly zero; f(a x + b z) = a f(x) + b f(z)."""
+    rng = np.random.default_rng(14)
+    d, rounds = 5, 3
+    ang = _rand_angles(rng, 2, rounds, d)
+    x = rng.standard_normal((9, 32))
+    z = rng.standard_normal((9, 32))
+    cls = rng.integers(0, 2, 9)
+    lhs = o.forward(2.5 * x - 1.5 * z, cls, ang)
+    rhs = 2.5 * o.forward(x, cls, ang) - 1.5 * o.forward(z, cls, ang)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12)
+    zero = o.forward(np.zeros((3, 32)), np.array([0, 1, 0]), ang)
+    assert np.all(zero == 0)
+
+
+def pin_class_routing(o):
+    """P13: each block uses its own class's table; permuting blocks permutes
+    outputs (checked against per-class matrices built independently)."""
+    rng = np.random.default_rng(15)
+    d, rounds, nc = 3, 2, 4
+    ang = _rand_angles(rng, nc, rounds, d)
+    mats = [o.transform_matrix_from_passes(ang[c]) for c in range(nc)]
+    x = rng.standard_normal((20, 8))
+    cls = rng.integers(0, nc, 20)
+    y = o.forward(x, cls, ang)
+    for b in range(20):
+        np.testing.assert_allclose(y[b], mats[cls[b]] @ x[b], rtol=0, atol=1e-13)
+    perm = rng.permutation(20)
+    np.testing.assert_allclose(o.forward(x[perm], cls[perm], ang), y[perm], rtol=0, atol=0)
+
+
+ALL_PINS = [pin_fig5_indices, pin_n2_worked, pin_zero_angles_identity,
+            pin_single_angle_layout, pin_pass_order, pin_kronecker,
+            pin_walsh_hadamard, pin_dense_product, pin_orthogonality,
+            pin_linearity_and_zero, pin_class_routing]
+
+
+@pytest.mark.parametrize("pin", ALL_PINS, ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin(orc)
+
+
+# ---------------------------------------------------------------------------
+# Parameter counts and printed Table II figures
+# ---------------------------------------------------------------------------
+
+def test_parameter_counts():
+    """P14: R N log2(N) / 2 angles (Sec. IV) at the workload sizes."""
+    assert orc.num_parameters(16, 2) == 64      # 4x4, R = 2: 2 * 4 * 8
+    assert orc.num_parameters(64, 4) == 768     # 8x8, R = 4
+    assert orc.num_parameters(256, 4) == 4096   # 16x16, R = 4
+    assert orc.num_parameters(64, 3) == 576
+    assert orc.num_parameters(64, 5) == 960
+    assert orc.klt_parameters(64) == 4096
+
+
+def _round_half_up(v):
+    return math.floor(v * 10 + 0.5 + 1e-12) / 10
+
+
+def test_table2_memory_ratios():
+    """P15: every memory-usage-ratio entry of Table II, to the printed decimal."""
+    g = _load("table2_memory_ratio.json")
+    for col, name in enumerate(g["columns"]):
+        s4, s8 = name.split("/")
+        for row in ("4x4", "8x8", "avg"):
+            got = orc.memory_usage_ratio(s4, s8, row)
+            # the table rounds half up (K/H(4) average is exactly 4.25 -> 4.3)
+            assert _round_half_up(got) == g[row][col], (name, row, got)
+
+
+def test_headline_memory_saving():
+    """Abstract: 6.8 times less memory than KLT matrices (the H(2)/H(3) scheme)."""
+    assert _round_half_up(orc.memory_usage_ratio("H(2)", "H(3)", "avg")) == 6.8
+
+
+# ---------------------------------------------------------------------------
+# Helpers: bf16 rounding and the dense transform
+# ---------------------------------------------------------------------------
+
+def test_round_to_bf16():
+    """bf16 keeps 8 significant bits: integers up to 256 are exact, 257 rounds
+    to 256 (tie to even), 259 to 260, 1 + 2^-8 to 1 (tie), 1 + 3*2^-9 up;
+    1e-3 = 1.024 * 2^-10 rounds to (1 + 3/128) * 2^-10."""
+    vals = np.array([0.0, -0.0, 1.0, 255.0, -255.0, 256.0, 257.0, 259.0,
+                     1 + 2 ** -8, 1 + 3 * 2 ** -9, 1e-3], dtype=np.float32)
+    got = orc.round_to_bf16(vals)
+    expect = [0.0, -0.0, 1.0, 255.0, -255.0, 256.0, 256.0, 260.0,
+              1.0, 1 + 2 ** -7, (1 + 3 / 128) * 2 ** -10]
+    np.testing.assert_array_equal(got, expect)
+
+
+def test_dense_transform_matches_hygt():
+    """eq. (3) with K_c = T_c reproduces the HyGT outputs."""
+    rng = np.random.default_rng(16)
+    ang = _rand_angles(rng, 3, 2, 4)
+    mats = np.stack([orc.transform_matrix_from_columns(ang[c]) for c in range(3)])
+    x = rng.standard_normal((11, 16))
+    cls = rng.integers(0, 3, 11)
+    np.testing.assert_allclose(orc.dense_transform(x, cls, mats),
+                               orc.forward(x, cls, ang), rtol=0, atol=1e-12)
+
+
+def test_rel_l2():
+    a = np.array([[3.0, 4.0], [0.0, 0.0]])
+    b = np.array([[3.0, 4.5], [0.0, 0.0]])
+    np.testing.assert_allclose(orc.rel_l2_per_block(b, a), [0.1, 0.0])
+    assert orc.rel_l2_global(a, a) == 0.0
+
+
+def test_input_validation():
+    with pytest.raises(ValueError):
+        orc.forward(np.zeros((2, 8)), np.array([0, 2]), np.zeros((2, 1, 3, 4)))
+    with pytest.raises(ValueError):
+        orc.forward(np.zeros((2, 8)), None, np.zeros((2, 1, 3, 4)))
+    with pytest.raises(ValueError):
+        orc.forward(np.zeros((2, 6)), None, np.zeros((1, 1, 3, 4)))
+    with pytest.raises(ValueError):
+        orc.pair_indices(3, 3)
+
+
+# ---------------------------------------------------------------------------
+# Mutation tests: plausible mistakes planted in a copy of the oracle must fail
+# ---------------------------------------------------------------------------
+
+class _Mutant:
+    """The oracle with one function replaced."""
+
+    def __init__(self, **overrides):
+        self._over = overrides
+
+    def __getattr__(self, name):
+        if name in self._over:
+            return self._over[name]
+        return getattr(orc, name)
+
+
+def _mutant_forward(sign=1.0, pass_order=None, pair_fn=None, drop_term=False):
+    def fwd(x, cls, angles):
+        x, cls, angles, rounds, d = orc._check(x, cls, angles)
+        v = x.copy()
+        for r in range(rounds):
+            ks = range(d) if pass_order is None else pass_order(d)
+            for k in ks:
+                m, n = (pair_fn or orc.pair_indices)(d, k)
+                th = angles[cls, r, k, :]
+                c, s = np.cos(th), sign * np.sin(th)
+                xm, xn = v[:, m].copy(), v[:, n].copy()
+                v[:, m] = c * xm + (0 if drop_term else s * xn)
+                v[:, n] = -s * xm + c * xn
+        return v
+    return fwd
+
+
+def _pairs_transposed(d, k):
+    # a plausible slip: reverse the j enumeration inside each pass
+    m, n = orc.pair_indices(d, k)
+    return m[::-1].copy(), n[::-1].copy()
+
+
+def _pairs_wrong_bit(d, k):
+    # another slip: pair along dimension d-1-k instead of k
+    return orc.pair_indices(d, d - 1 - k)
+
+
+def _build_mutants():
+    def cols(fwd):
+        def t_from_cols(angles_c):
+            angles_c = np.asarray(angles_c, dtype=np.float64)
+            n_el = 1 << angles_c.shape[1]
+            return fwd(np.eye(n_el), np.zeros(n_el, dtype=np.int64), angles_c[None]).T
+        return t_from_cols
+
+    out = {}
+    for name, fwd in {
+        "sign_flipped": _mutant_forward(sign=-1.0),
+        "passes_reversed": _mutant_forward(pass_order=lambda d: reversed(range(d))),
+        "pairs_enumerated_backwards": _mutant_forward(pair_fn=_pairs_transposed),
+        "wrong_hypercube_dimension": _mutant_forward(pair_fn=_pairs_wrong_bit),
+        "dropped_term": _mutant_forward(drop_term=True),
+    }.items():
+        out[name] = _Mutant(forward=fwd, transform_matrix_from_columns=cols(fwd))
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(_build_mutants().keys()))
+def test_pins_catch_mutant(name):
+    mutant = _build_mutants()[name]
+    failures = 0
+    for pin in ALL_PINS:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"no pin caught mutant {name}"
