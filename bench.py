@@ -1,0 +1,179 @@
+"""HyGT throughput benchmark on one MI355X.
+
+Workload (8x8 blocks): 2^20 blocks of N = 64 FP32 residuals (separable 2-D
+AR(1), rho = 0.9, sigma = 40, rounded to integers in [-255, 255]), a class per
+block uniform over 35 classes, 35 angle tables of R = 4 rounds (768 angles
+each, uniform in [-pi, pi)). One step = the whole hot path on that batch:
+plan (multiplier tables + class grouping), forward transform, inverse
+transform. Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: blocks/s for forward + inverse, the roofline of the
+dominant kernel (the forward rotation, timed with HIP events on the stream it
+runs on), and the FP64 oracle timed on a bounded sample on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak, GB/s
+NBLOCKS = 1 << 20
+LOG2N = 6
+N = 1 << LOG2N
+ROUNDS = 4
+NCLASSES = 35
+# algorithmic HBM bytes per block and direction: read N floats, write N floats,
+# read the 4-byte class index (angle tables are < 0.1% and not counted)
+BYTES_PER_BLOCK = 4 * N + 4 * N + 4
+FLOPS_PER_BLOCK = 6 * ROUNDS * LOG2N * (N // 2)
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16,
+                    help="blocks of the batch run through the oracle on the host (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 256 MiB device copies (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def _copy_calibration(torch, dev):
+    a = torch.empty(NBLOCKS * N, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                      "launches": 5}))
+
+
+def _cpu_baseline(x, cls, ang, sample):
+    from oracle import hygt_oracle as orc
+
+    xs, cs = x[:sample], cls[:sample]
+    t0 = time.perf_counter()
+    y = orc.forward(xs, cs, ang)
+    orc.inverse(y, cs, ang)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "blocks/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample} blocks of the batch, forward + inverse, FP64 NumPy, "
+                      f"one process ({dt:.1f} s)"}
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(blocks are independent, so N GPUs would each run this batch on their own "
+              "share with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2505_21728_amd as hygt
+    from paper_2505_21728_amd import synth
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        _copy_calibration(torch, dev)
+        return
+
+    ang = synth.angles(NCLASSES, ROUNDS, LOG2N)
+    x = synth.ar1_blocks(NBLOCKS, 8)
+    cls = synth.classes(NBLOCKS, NCLASSES)
+    xt = torch.from_numpy(x).to(dev)
+    ct = torch.from_numpy(cls).to(dev)
+    at = torch.from_numpy(ang).to(dev)
+    yt = torch.empty_like(xt)
+    zt = torch.empty_like(xt)
+    ws = torch.empty(hygt.workspace_bytes(NBLOCKS, LOG2N, ROUNDS, NCLASSES),
+                     dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+
+    def step(events=None):
+        plan = hygt.Plan(at, ct, workspace=ws)
+        if events:
+            events[0].record(stream)
+        plan.forward(xt, out=yt)
+        if events:
+            events[1].record(stream)
+            events[2].record(stream)
+        plan.inverse(yt, out=zt)
+        if events:
+            events[3].record(stream)
+        return plan
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan = step()
+    plan.check()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(ev[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    inv_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / args.steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = NBLOCKS / (ms_per_step / 1e3)
+    launch_bytes = NBLOCKS * BYTES_PER_BLOCK
+    achieved = launch_bytes / (fwd_ms / 1e3) / 1e9
+    step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = _cpu_baseline(x, cls, ang, min(args.cpu_sample, NBLOCKS))
+
+    out = {
+        "metric": "blocks/sec and achieved HBM GB/s (% peak), HyGT fwd+inv N=64",
+        "value": value,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "HyGT 8x8 blocks fwd+inv: 2^20 blocks, N=64, R=4, 35 classes, "
+                               "AR(1) rho=0.9 sigma=40 int-valued FP32",
+                   "nblocks": NBLOCKS, "N": N, "rounds": ROUNDS, "classes": NCLASSES},
+        "step_hbm_gbps": step_gbps,
+        "step_pct_peak": 100.0 * step_gbps / HBM_PEAK_GBPS,
+        "fwd_ms": fwd_ms,
+        "inv_ms": inv_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "rotate_kernel<6,0,4> (forward)",
+                     "bytes_per_launch": launch_bytes,
+                     "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,143 @@
+/*
+ * hygt.h - batched Hypercube-Givens transforms (HyGT) on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The transform is the one of Said, Zhao, Karczewicz, Egilmez, Seregin, Chen,
+ * "Highly Efficient Non-Separable Transforms for Next Generation Video
+ * Coding" (arXiv 2505.21728):
+ *
+ *   - A block is a vector of N = 2^log2n residuals (Sec. II: the residual
+ *     vector r = x - p of one video block). A 2^B x 2^B pixel block is stored
+ *     in row-major raster order (index = row * 2^B + col).
+ *   - Each block carries a class index c (Sec. II: the classification index
+ *     chosen per block); each class has its own angle set (Sec. III: one set
+ *     of parameter vectors per class).
+ *   - One pass rotates every index pair (i, i XOR 2^k) by its own angle with
+ *     the Givens matrix of Sec. IV: y_m = cos*x_m + sin*x_n,
+ *     y_n = -sin*x_m + cos*x_n, where m is the index of the pair whose bit k
+ *     is 0 (the parallel-Givens matrix of eq. (8)).
+ *   - A round is log2n passes, k = 0, 1, ..., log2n-1 (Sec. IV, hypercube
+ *     dimensions taken in turn). The transform is R rounds; the first pass
+ *     applied is round 0, pass 0 (the factor F_1 of eq. (5)).
+ *   - Angle j of pass k belongs to the pair whose lower index m is j with a
+ *     zero bit inserted at bit position k, upper index n = m + 2^k (the index
+ *     arrays of Fig. 5). There are R * N * log2n / 2 angles per class (Sec. IV).
+ *   - The inverse applies the passes in reverse order with negated angles
+ *     (eq. (6), eq. (9), Sec. IV); it equals the transpose.
+ *   - The optional final permutation pass of Fig. 4 is not applied.
+ *
+ * Memory and ownership
+ *   Every array argument is DEVICE memory owned by the caller. The library
+ *   allocates nothing, keeps no state between calls and never synchronises
+ *   the stream except in hygt_check_error(). All work is enqueued on `stream`
+ *   (0 = the null stream) and runs asynchronously.
+ *
+ * Layouts
+ *   x, y     float32 [nblocks][N], contiguous, 16-byte aligned.
+ *            y == x (in place) is allowed; any other overlap is rejected.
+ *   cls      int32 [nblocks], class of each block in [0, nclasses).
+ *            May be NULL when nclasses == 1 (every block is class 0).
+ *   Any array pointer may be NULL when nblocks == 0.
+ *   angles   float32 [nclasses][rounds][log2n][N/2], contiguous, radians.
+ *   workspace  at least hygt_workspace_bytes(...) bytes, 256-byte aligned.
+ *            Holds the class grouping and the per-class multiplier tables
+ *            built by hygt_plan(); it needs no initialisation.
+ *
+ * Limits
+ *   1 <= log2n <= 8, 1 <= rounds <= HYGT_MAX_ROUNDS,
+ *   1 <= nclasses <= HYGT_MAX_CLASSES, 0 <= nblocks <= HYGT_MAX_BLOCKS.
+ *   Inputs are expected to be finite with Euclidean block norm below 2^90;
+ *   within that range every output is within a few FP32 ulps per pass of the
+ *   exact transform (relative L2 well under 1e-5 for the sizes above).
+ *
+ * Errors
+ *   Every entry point returns a status. Host-side validation failures return
+ *   HYGT_EINVAL or HYGT_EWORKSPACE and enqueue nothing. nblocks == 0 is a
+ *   successful no-op. A class index outside [0, nclasses) is detected on the
+ *   device: that block is left unwritten and a flag is set in the workspace,
+ *   which hygt_check_error() reports as HYGT_ECLASS.
+ *
+ * Determinism
+ *   Each block's result depends only on that block's values, its class and
+ *   the angle table: it is bit-identical whatever the batch it is in, the
+ *   batch order, or in-place versus out-of-place execution.
+ */
+#ifndef HYGT_H
+#define HYGT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hygt_status {
+    HYGT_OK = 0,
+    HYGT_EINVAL = -1,     /* an argument is out of range, NULL or misaligned */
+    HYGT_EWORKSPACE = -2, /* workspace NULL, too small or not 256-byte aligned */
+    HYGT_ELAUNCH = -3,    /* the HIP runtime refused a kernel launch */
+    HYGT_ECLASS = -4,     /* a block's class index was outside [0, nclasses) */
+    HYGT_EHIP = -5        /* another HIP runtime error (hygt_check_error) */
+};
+
+enum hygt_direction {
+    HYGT_FORWARD = 0, /* y = T_c x   (eq. (5)) */
+    HYGT_INVERSE = 1  /* y = T_c^-1 x = T_c^T x   (eq. (6), eq. (9)) */
+};
+
+#define HYGT_MAX_LOG2N 8
+#define HYGT_MAX_ROUNDS 64
+#define HYGT_MAX_CLASSES 4096
+#define HYGT_MAX_BLOCKS 2147483647LL
+
+/* Size in bytes of the workspace needed for these sizes (0 for invalid
+ * sizes). The same workspace serves hygt_plan, hygt_apply, hygt_forward and
+ * hygt_inverse for these sizes. */
+size_t hygt_workspace_bytes(int64_t nblocks, int log2n, int rounds, int nclasses);
+
+/* Builds, in the workspace, everything that depends on the classes and the
+ * angles but not on the data:
+ *   - the multiplier tables of both directions: cos and sin of every angle,
+ *     evaluated in FP64 (the paper's "conversion to higher precision
+ *     multipliers", Sec. IV) and folded into per-pass FP32 coefficients;
+ *   - a grouping of the blocks by class into tiles of 64 blocks of one class.
+ * cls is read; angles is read. Both may be reused or freed once the stream
+ * reaches the end of this call's work. */
+int hygt_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
+              const float* angles, int nclasses,
+              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Applies the planned transform (direction HYGT_FORWARD or HYGT_INVERSE) to
+ * x, writing y. The sizes must be those given to the hygt_plan() call that
+ * filled the workspace; the plan may be applied any number of times, in both
+ * directions, until the workspace is planned again. */
+int hygt_apply(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+               int nclasses, int direction,
+               const void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* hygt_plan() followed by hygt_apply(HYGT_FORWARD): y[b] = T_{cls[b]} x[b]. */
+int hygt_forward(const float* x, float* y, const int32_t* cls, int64_t nblocks,
+                 int log2n, int rounds, const float* angles, int nclasses,
+                 void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* hygt_plan() followed by hygt_apply(HYGT_INVERSE): y[b] = T_{cls[b]}^T x[b]. */
+int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks,
+                 int log2n, int rounds, const float* angles, int nclasses,
+                 void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Waits for `stream`, then reports whether the last plan or apply on this
+ * workspace met a class index outside [0, nclasses) (HYGT_ECLASS), a HIP
+ * error (HYGT_EHIP), or neither (HYGT_OK). */
+int hygt_check_error(const void* workspace, hipStream_t stream);
+
+/* A static, human-readable description of a status code. */
+const char* hygt_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYGT_H */

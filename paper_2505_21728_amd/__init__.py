@@ -1,0 +1,153 @@
+"""Batched Hypercube-Givens transforms (HyGT) on AMD Instinct MI355X (gfx950).
+
+The transforms are those of Said et al., "Highly Efficient Non-Separable
+Transforms for Next Generation Video Coding" (arXiv 2505.21728), Sec. IV.
+All computation runs in the HIP kernels of libhygt.so (include/hygt.h); this
+module checks tensor arguments and passes device pointers and the current
+stream through the C ABI. PyTorch provides device memory and streams only.
+
+    plan = Plan(angles, cls)          # angles [C, R, d, N/2] f32, cls [B] i32 (cuda)
+    y = plan.forward(x)               # x [B, N] f32 (cuda): y[b] = T_cls[b] x[b]
+    z = plan.inverse(y)               # z[b] = T_cls[b]^T y[b]
+"""
+
+from __future__ import annotations
+
+import math
+
+from . import _abi
+from ._abi import (HYGT_FORWARD, HYGT_INVERSE, HYGT_MAX_BLOCKS, HYGT_MAX_CLASSES,
+                   HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS, HygtError)
+
+__all__ = ["Plan", "forward", "inverse", "workspace_bytes", "HygtError",
+           "HYGT_FORWARD", "HYGT_INVERSE"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _require(cond: bool, msg: str, exc=ValueError):
+    if not cond:
+        raise exc(msg)
+
+
+def workspace_bytes(nblocks: int, log2n: int, rounds: int, nclasses: int) -> int:
+    return _abi.hygt_workspace_bytes(nblocks, log2n, rounds, nclasses)
+
+
+class Plan:
+    """Class grouping and multiplier tables for one batch of class indices.
+
+    The plan reads `angles` and `cls` once (on the current stream) and keeps
+    everything the transform needs in a device workspace, so it can be applied
+    to any number of [B, N] arrays in either direction.
+    """
+
+    def __init__(self, angles, cls=None, nblocks: int | None = None, stream=None,
+                 workspace=None):
+        torch = _torch()
+        _require(isinstance(angles, torch.Tensor), "angles must be a torch.Tensor", TypeError)
+        _require(angles.is_cuda, "angles must be on a HIP device")
+        _require(angles.dtype == torch.float32, "angles must be float32", TypeError)
+        _require(angles.dim() == 4, "angles must be [nclasses, rounds, log2n, N/2]")
+        _require(angles.is_contiguous(), "angles must be contiguous")
+        nclasses, rounds, log2n, half = (int(s) for s in angles.shape)
+        _require(1 <= log2n <= HYGT_MAX_LOG2N, f"log2n must be in [1, {HYGT_MAX_LOG2N}]")
+        _require(half == 1 << (log2n - 1), "angles last dimension must be N/2 = 2^(log2n-1)")
+        _require(1 <= rounds <= HYGT_MAX_ROUNDS, f"rounds must be in [1, {HYGT_MAX_ROUNDS}]")
+        _require(1 <= nclasses <= HYGT_MAX_CLASSES,
+                 f"nclasses must be in [1, {HYGT_MAX_CLASSES}]")
+        if cls is None:
+            _require(nclasses == 1, "cls may be omitted only when there is one class")
+            _require(nblocks is not None, "give nblocks when cls is omitted")
+        else:
+            _require(isinstance(cls, torch.Tensor), "cls must be a torch.Tensor", TypeError)
+            _require(cls.is_cuda and cls.device == angles.device,
+                     "cls must be on the same device as angles")
+            _require(cls.dtype == torch.int32, "cls must be int32", TypeError)
+            _require(cls.dim() == 1 and cls.is_contiguous(), "cls must be a contiguous [nblocks]")
+            _require(nblocks is None or nblocks == cls.numel(), "nblocks does not match cls")
+            nblocks = cls.numel()
+        _require(0 <= nblocks <= HYGT_MAX_BLOCKS, "nblocks out of range")
+
+        self.device = angles.device
+        self.nblocks = int(nblocks)
+        self.log2n = log2n
+        self.n = 1 << log2n
+        self.rounds = rounds
+        self.nclasses = nclasses
+        self.ws_bytes = workspace_bytes(self.nblocks, log2n, rounds, nclasses)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        _require(workspace.is_cuda and workspace.dtype == torch.uint8 and
+                 workspace.numel() >= self.ws_bytes, "workspace too small")
+        _require(workspace.data_ptr() % 256 == 0, "workspace must be 256-byte aligned")
+        self.workspace = workspace
+        self._stream = stream
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_plan(0 if cls is None else cls.data_ptr(), self.nblocks, log2n,
+                                rounds, angles.data_ptr(), nclasses, workspace.data_ptr(),
+                                self.ws_bytes, _stream_handle(stream))
+        _abi._check(st, "hygt_plan")
+
+    def _check_x(self, x):
+        torch = _torch()
+        _require(isinstance(x, torch.Tensor), "x must be a torch.Tensor", TypeError)
+        _require(x.device == self.device, "x must be on the plan's device")
+        _require(x.dtype == torch.float32, "x must be float32", TypeError)
+        _require(x.dim() == 2 and tuple(x.shape) == (self.nblocks, self.n),
+                 f"x must be [{self.nblocks}, {self.n}]")
+        _require(x.is_contiguous(), "x must be contiguous")
+
+    def apply(self, x, direction: int, out=None):
+        torch = _torch()
+        self._check_x(x)
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            self._check_x(out)
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_apply(x.data_ptr(), out.data_ptr(), self.nblocks, self.log2n,
+                                 self.rounds, self.nclasses, direction,
+                                 self.workspace.data_ptr(), self.ws_bytes,
+                                 _stream_handle(self._stream))
+        _abi._check(st, "hygt_apply")
+        return out
+
+    def forward(self, x, out=None):
+        """y[b] = T_{cls[b]} x[b] (eq. (5))."""
+        return self.apply(x, HYGT_FORWARD, out)
+
+    def inverse(self, x, out=None):
+        """y[b] = T_{cls[b]}^T x[b] (eq. (6) and (9))."""
+        return self.apply(x, HYGT_INVERSE, out)
+
+    def check(self):
+        """Synchronises and raises HygtError if a class index was out of range."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_check_error(self.workspace.data_ptr(), _stream_handle(self._stream))
+        _abi._check(st, "hygt_check_error")
+
+
+def forward(x, cls, angles, out=None):
+    """One-shot y[b] = T_{cls[b]} x[b]."""
+    return Plan(angles, cls, nblocks=x.shape[0]).forward(x, out)
+
+
+def inverse(x, cls, angles, out=None):
+    """One-shot y[b] = T_{cls[b]}^T x[b]."""
+    return Plan(angles, cls, nblocks=x.shape[0]).inverse(x, out)
+
+
+def num_angles(n: int, rounds: int) -> int:
+    """R * N * log2(N) / 2 angles per class (Sec. IV)."""
+    return rounds * n * int(math.log2(n)) // 2

@@ -1,0 +1,124 @@
+"""ctypes binding of libhygt.so: argument marshalling only.
+
+Every entry point of include/hygt.h is exposed under the same name. Pointers
+are passed as integers (``tensor.data_ptr()``), streams as the raw HIP stream
+handle (``torch.cuda.Stream.cuda_stream``). No computation happens here.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhygt.so")
+
+HYGT_OK = 0
+HYGT_EINVAL = -1
+HYGT_EWORKSPACE = -2
+HYGT_ELAUNCH = -3
+HYGT_ECLASS = -4
+HYGT_EHIP = -5
+
+HYGT_FORWARD = 0
+HYGT_INVERSE = 1
+
+HYGT_MAX_LOG2N = 8
+HYGT_MAX_ROUNDS = 64
+HYGT_MAX_CLASSES = 4096
+HYGT_MAX_BLOCKS = 2147483647
+
+# Every exported symbol with its (restype, argtypes).
+_c = ctypes
+_SIGNATURES = {
+    "hygt_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int, _c.c_int, _c.c_int]),
+    "hygt_plan": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int, _c.c_void_p,
+                             _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_apply": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
+                              _c.c_int, _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_forward": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int,
+                                _c.c_int, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_size_t,
+                                _c.c_void_p]),
+    "hygt_inverse": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int,
+                                _c.c_int, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_size_t,
+                                _c.c_void_p]),
+    "hygt_check_error": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "hygt_strerror": (_c.c_char_p, [_c.c_int]),
+}
+
+_lib = None
+
+
+class HygtError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+def load() -> ctypes.CDLL:
+    """Loads libhygt.so once; raises if the extension has not been built.
+
+    torch is imported first so that the library binds to the same HIP runtime
+    that owns the tensors and streams passed to it.
+    """
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (shares its HIP runtime with the library)
+
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP extension first "
+            "(python -m paper_2505_21728_amd.build or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGNATURES)
+
+
+def strerror(status: int) -> str:
+    return load().hygt_strerror(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != HYGT_OK:
+        raise HygtError(status, where)
+
+
+def hygt_workspace_bytes(nblocks: int, log2n: int, rounds: int, nclasses: int) -> int:
+    return int(load().hygt_workspace_bytes(nblocks, log2n, rounds, nclasses))
+
+
+def hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr, ws_bytes,
+              stream) -> int:
+    return load().hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
+                            ws_bytes, stream)
+
+
+def hygt_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr, ws_bytes,
+               stream) -> int:
+    return load().hygt_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr,
+                             ws_bytes, stream)
+
+
+def hygt_forward(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
+                 ws_bytes, stream) -> int:
+    return load().hygt_forward(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr,
+                               nclasses, ws_ptr, ws_bytes, stream)
+
+
+def hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
+                 ws_bytes, stream) -> int:
+    return load().hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr,
+                               nclasses, ws_ptr, ws_bytes, stream)
+
+
+def hygt_check_error(ws_ptr, stream) -> int:
+    return load().hygt_check_error(ws_ptr, stream)

@@ -1,0 +1,117 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load and export every entry point of include/hygt.h, and its
+argument validation must reject bad calls before anything reaches the HIP
+runtime. Pointers passed here are never dereferenced: every call below fails
+validation (or is an nblocks == 0 no-op) on the host.
+"""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2505_21728_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hygt.h")
+
+FAKE = 1 << 20          # a 256-byte aligned non-null address (never dereferenced)
+FAKE_MISALIGNED = FAKE + 4
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(hygt_\w+)\s*\(", text, re.M)))
+
+
+def test_library_built():
+    assert os.path.exists(_abi.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_exports_every_declared_symbol():
+    declared = _declared_functions()
+    assert declared == sorted(_abi.exported_symbols())
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(hygt_\w+)", out))
+    for name in declared:
+        assert name in exported, name
+    lib = _abi.load()
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_strerror():
+    for st in (0, -1, -2, -3, -4, -5):
+        assert _abi.strerror(st)
+    assert "unknown" in _abi.strerror(123)
+
+
+def test_workspace_bytes():
+    ws = _abi.hygt_workspace_bytes
+    assert ws(0, 4, 2, 1) > 0
+    assert ws(4096, 4, 2, 1) >= 4096 * 4
+    big = ws(1 << 20, 6, 4, 35)
+    # grouping (perm 4 B/block + tiles) and tables for both directions
+    assert big >= (1 << 20) * 4 + 2 * 35 * 24 * 128 * 4
+    assert ws(1 << 20, 6, 4, 35) < ws(1 << 21, 6, 4, 35)
+    for bad in [(-1, 4, 2, 1), (10, 0, 2, 1), (10, 9, 2, 1), (10, 4, 0, 1),
+                (10, 4, 65, 1), (10, 4, 2, 0), (10, 4, 2, 4097), (1 << 31, 4, 2, 1)]:
+        assert ws(*bad) == 0, bad
+
+
+@pytest.mark.parametrize("args", [
+    # cls, nblocks, log2n, rounds, angles, nclasses
+    (FAKE, 10, 0, 2, FAKE, 1),
+    (FAKE, 10, 9, 2, FAKE, 1),
+    (FAKE, 10, 4, 0, FAKE, 1),
+    (FAKE, 10, 4, 2, FAKE, 0),
+    (FAKE, -1, 4, 2, FAKE, 1),
+    (FAKE, 10, 4, 2, 0, 1),          # angles NULL
+    (FAKE, 10, 4, 2, FAKE + 2, 1),   # angles misaligned
+    (0, 10, 4, 2, FAKE, 3),          # cls NULL with several classes
+    (FAKE + 2, 10, 4, 2, FAKE, 3),   # misaligned cls
+])
+def test_plan_rejects(args):
+    cls, nb, d, r, ang, nc = args
+    ws_bytes = 1 << 30
+    assert _abi.hygt_plan(cls, nb, d, r, ang, nc, FAKE, ws_bytes, 0) == _abi.HYGT_EINVAL
+
+
+def test_plan_workspace_checks():
+    need = _abi.hygt_workspace_bytes(100, 4, 2, 3)
+    assert _abi.hygt_plan(FAKE, 100, 4, 2, FAKE, 3, 0, need, 0) == _abi.HYGT_EWORKSPACE
+    assert _abi.hygt_plan(FAKE, 100, 4, 2, FAKE, 3, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert _abi.hygt_plan(FAKE, 100, 4, 2, FAKE, 3, FAKE_MISALIGNED, need, 0) == \
+        _abi.HYGT_EWORKSPACE
+    # nblocks == 0 is a successful no-op that enqueues nothing, NULL arrays allowed
+    assert _abi.hygt_plan(FAKE, 0, 4, 2, FAKE, 3, FAKE, need, 0) == _abi.HYGT_OK
+    need0 = _abi.hygt_workspace_bytes(0, 4, 2, 3)
+    assert _abi.hygt_plan(0, 0, 4, 2, 0, 3, FAKE, need0, 0) == _abi.HYGT_OK
+
+
+def test_apply_rejects():
+    need = _abi.hygt_workspace_bytes(100, 4, 2, 3)
+    a = _abi.hygt_apply
+    x, y = FAKE, FAKE * 4
+    assert a(x, y, 100, 4, 2, 3, 2, FAKE, need, 0) == _abi.HYGT_EINVAL          # direction
+    assert a(0, y, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL           # x NULL
+    assert a(x, 0, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL           # y NULL
+    assert a(x + 8, y, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL       # x misaligned
+    assert a(x, x + 64, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL      # overlap
+    assert a(x, y, 100, 4, 2, 3, 0, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert a(x, y, 0, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_OK                 # no-op
+    # N == 2 blocks need only 8-byte alignment
+    need2 = _abi.hygt_workspace_bytes(100, 1, 2, 1)
+    assert a(x + 8, y + 8, 0, 1, 2, 1, 0, FAKE, need2, 0) == _abi.HYGT_OK
+
+
+def test_forward_inverse_reject_before_planning():
+    need = _abi.hygt_workspace_bytes(100, 6, 4, 35)
+    for fn in (_abi.hygt_forward, _abi.hygt_inverse):
+        # overlapping x / y: rejected before the plan is enqueued
+        assert fn(FAKE, FAKE + 256, FAKE, 100, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_EINVAL
+        assert fn(0, FAKE, FAKE, 100, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_EINVAL
+        assert fn(FAKE, FAKE * 8, FAKE, 0, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_OK
