@@ -41,7 +41,8 @@
  *   angles   float32 [nclasses][rounds][log2n][N/2], contiguous, radians.
  *   workspace  at least hygt_workspace_bytes(...) bytes, 256-byte aligned.
  *            Holds the class grouping and the per-class multiplier tables
- *            built by hygt_plan(); it needs no initialisation.
+ *            built by hygt_plan(); it needs no initialisation. Calls that
+ *            use one workspace must be ordered (one stream, or events).
  *
  * Limits
  *   1 <= log2n <= 8, 1 <= rounds <= HYGT_MAX_ROUNDS,
@@ -99,11 +100,12 @@ enum hygt_direction {
 size_t hygt_workspace_bytes(int64_t nblocks, int log2n, int rounds, int nclasses);
 
 /* Builds, in the workspace, everything that depends on the classes and the
- * angles but not on the data:
+ * angles but not on the data (one kernel launch):
  *   - the multiplier tables of both directions: cos and sin of every angle,
  *     evaluated in FP64 (the paper's "conversion to higher precision
  *     multipliers", Sec. IV) and folded into per-pass FP32 coefficients;
- *   - a grouping of the blocks by class into tiles of 64 blocks of one class.
+ *   - a grouping of the blocks by class into tiles of 64 blocks of one class
+ *     (per chunk of 16384 consecutive blocks).
  * cls is read; angles is read. Both may be reused or freed once the stream
  * reaches the end of this call's work. */
 int hygt_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
@@ -128,10 +130,11 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks,
                  int log2n, int rounds, const float* angles, int nclasses,
                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* Waits for `stream`, then reports whether the last plan or apply on this
+/* Waits for `stream`, then reports whether the last non-empty plan on this
  * workspace met a class index outside [0, nclasses) (HYGT_ECLASS), a HIP
- * error (HYGT_EHIP), or neither (HYGT_OK). */
-int hygt_check_error(const void* workspace, hipStream_t stream);
+ * error (HYGT_EHIP), or neither (HYGT_OK). Reads at most workspace_bytes
+ * bytes of the workspace. */
+int hygt_check_error(const void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* A static, human-readable description of a status code. */
 const char* hygt_strerror(int status);

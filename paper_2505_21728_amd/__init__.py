@@ -134,7 +134,8 @@ class Plan:
         """Synchronises and raises HygtError if a class index was out of range."""
         torch = _torch()
         with torch.cuda.device(self.device):
-            st = _abi.hygt_check_error(self.workspace.data_ptr(), _stream_handle(self._stream))
+            st = _abi.hygt_check_error(self.workspace.data_ptr(), self.ws_bytes,
+                                       _stream_handle(self._stream))
         _abi._check(st, "hygt_check_error")
 
 

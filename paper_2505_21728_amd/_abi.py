@@ -42,7 +42,7 @@ _SIGNATURES = {
     "hygt_inverse": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int,
                                 _c.c_int, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_size_t,
                                 _c.c_void_p]),
-    "hygt_check_error": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "hygt_check_error": (_c.c_int, [_c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_strerror": (_c.c_char_p, [_c.c_int]),
 }
 
@@ -120,5 +120,5 @@ def hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, ncla
                                nclasses, ws_ptr, ws_bytes, stream)
 
 
-def hygt_check_error(ws_ptr, stream) -> int:
-    return load().hygt_check_error(ws_ptr, stream)
+def hygt_check_error(ws_ptr, ws_bytes, stream) -> int:
+    return load().hygt_check_error(ws_ptr, ws_bytes, stream)

@@ -5,6 +5,7 @@
 #include "hygt.h"
 
 #include <cstdint>
+#include <vector>
 
 #include "hygt_internal.h"
 
@@ -118,14 +119,24 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks, 
                           workspace, workspace_bytes, stream);
 }
 
-int hygt_check_error(const void* workspace, hipStream_t stream) {
-    if (workspace == nullptr || !aligned(workspace, 256)) return HYGT_EWORKSPACE;
+int hygt_check_error(const void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (workspace == nullptr || !aligned(workspace, 256) ||
+        workspace_bytes < sizeof(hygt::PlanHeader))
+        return HYGT_EWORKSPACE;
     if (hipStreamSynchronize(stream) != hipSuccess) return HYGT_EHIP;
-    int32_t err = 0;
-    const auto* hdr = static_cast<const hygt::PlanHeader*>(workspace);
-    if (hipMemcpy(&err, &hdr->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+    const auto* base = static_cast<const char*>(workspace);
+    hygt::PlanHeader hdr;
+    if (hipMemcpy(&hdr, base, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess) return HYGT_EHIP;
+    // per-chunk flags follow the header (see ws_layout)
+    const size_t nchunks = hdr.nchunks > 0 ? static_cast<size_t>(hdr.nchunks) : 0;
+    if (sizeof(hygt::PlanHeader) + nchunks * 4 > workspace_bytes) return HYGT_EWORKSPACE;
+    std::vector<int32_t> flags(nchunks);
+    if (nchunks && hipMemcpy(flags.data(), base + sizeof(hygt::PlanHeader), nchunks * 4,
+                             hipMemcpyDeviceToHost) != hipSuccess)
         return HYGT_EHIP;
-    return err ? HYGT_ECLASS : HYGT_OK;
+    for (int32_t f : flags)
+        if (f) return HYGT_ECLASS;
+    return HYGT_OK;
 }
 
 const char* hygt_strerror(int status) {

@@ -3,32 +3,33 @@
 //
 // Multiplier tables. Sec. IV of the paper keeps the transform parameters
 // compact and converts them to higher-precision multipliers only when they
-// are needed. Here the conversion evaluates cos and sin of every FP32 angle in
-// FP64 and folds them into per-pass FP32 coefficients for one of two
-// evaluation forms of the Givens butterfly (Sec. IV element definition):
+// are needed. Here every FP32 angle is converted, in FP64, into the two
+// multipliers of a lifting (three-shear) form of its Givens rotation, rounded
+// once to FP32:
 //
-//   direct:  y_m = (c s_m) a + (s s_n) b,  y_n = (c s_n) b - (s s_m) a
-//   scaled:  y_m = a + t_m b,  y_n = b + t_n a,
-//            t_m = s s_n / (c s_m),  t_n = -s s_m / (c s_n)
+//   a += p*b;  b += q*a;  a += p*b      p = tan(phi/2), q = -sin(phi)
 //
-// where a, b are the stored values of elements m, n and s_m, s_n their scale
-// factors (true value = scale * stored value). The scaled form costs two FMAs
-// per butterfly instead of four operations and leaves the outputs scaled by
-// c s_m and c s_n (a square-root-free Givens rotation); the direct form costs
-// four and returns unscaled outputs. A class normally runs the scaled
-// schedule: every pass scaled except the last, which is direct so that the
-// stored result is the true result. If its angles would push a scale factor
-// below 2^-64 (cosines near zero), the class runs the direct schedule, every
-// pass direct with unit scales. Both give the exact rotation in exact
-// arithmetic; the choice depends only on the angles, so every block of a
-// class follows the same arithmetic.
+// which applies y_m = cos(phi) a + sin(phi) b, y_n = -sin(phi) a + cos(phi) b
+// (the Sec. IV element definition) in place, with three FMAs and no
+// temporary. The angle is first reduced to |phi| <= pi/2, using
+// G(theta) = -G(theta -/+ pi), so that |p|, |q| <= 1 and every step is well
+// conditioned. The resulting sign flips are tracked per element through the
+// passes: an element stored with sign s holds s times its true value, a pair
+// whose two signs differ is rotated by -phi instead (G(phi) diag(1,-1) =
+// diag(1,-1) G(-phi)), and the signs left at the end are applied to the
+// outputs. Both the reduction and the sign bookkeeping depend only on the
+// angles, so every block of a class follows the same arithmetic.
 //
 // Grouping. A tile is 64 blocks of one class, so that a wavefront (one lane
-// per block) reads one class table with scalar loads. The grouping is a
-// counting sort by class: a histogram with LDS-local counts, an exclusive scan
-// done by the last histogram workgroup to finish, and a scatter that reserves
-// per-class ranges with one atomic per class per workgroup.
+// per block) reads one class table with scalar loads. Tiles are sorted by
+// class over the whole batch, so that the wavefronts of a compute unit pair
+// mostly share one class and its table stays in their scalar cache. The
+// counting sort takes two launches over chunks of consecutive blocks: the
+// first counts the classes of each chunk (beside the table builders), the
+// second gives every chunk its start inside each class from the counts of
+// the chunks before it and scatters the block ids into the class's tiles.
 
+#include <algorithm>
 #include <cmath>
 
 #include "hygt_internal.h"
@@ -41,215 +42,249 @@ __device__ __forceinline__ int insert_zero_bit(int j, int k) {
     return ((j >> k) << (k + 1)) | (j & ((1 << k) - 1));
 }
 
-// One workgroup per (direction, class) builds that table; one extra
-// workgroup resets the counters used by the grouping kernels.
-__global__ __launch_bounds__(kTableThreads) void plan_tables_kernel(
-    const float* __restrict__ angles, int log2n, int rounds, int nclasses, int grouped,
-    float* __restrict__ coef, int32_t* __restrict__ modes, PlanHeader* __restrict__ hdr,
-    int32_t* __restrict__ counts) {
+// Angles converted per parallel sweep of a table builder.
+constexpr int kAngleBatch = 2048;
+// Entries of the per-chunk class counts cached in LDS by the placing kernel.
+constexpr int kCountsCache = 16384;
+
+struct PlanShared {
+    union {
+        struct {  // table builders
+            int sign[256];
+            float tanh_phi[kAngleBatch];  // tan(phi/2) of the batch's angles
+            float sin_phi[kAngleBatch];   // sin(phi)
+            signed char flip[kAngleBatch];  // -1 where |theta| > pi/2
+        } t;
+        struct {  // chunk counting
+            int hist[4096];
+        } c;
+        struct {  // chunk placing
+            int counts[kCountsCache];
+            int total[4096];      // blocks of each class in the batch
+            int pre[4096];        // blocks of each class in earlier chunks
+            int tile_base[4097];  // first tile of each class
+            int pos[4096];        // blocks of each class placed by this chunk so far
+            int scan[kPlanThreads];
+        } p;
+    };
+    int flag;
+};
+
+// Multiplier table of one (direction, class); see the file comment. The
+// FP64 conversion of a batch of angles runs in parallel; only the sign walk
+// through the passes is sequential.
+__device__ void build_table(PlanShared& sh, int dir, int c, const float* __restrict__ angles,
+                            int log2n, int rounds, int nclasses, float* __restrict__ coef,
+                            float* __restrict__ signs, int32_t* __restrict__ modes) {
     const int tid = threadIdx.x;
-    const int wg = blockIdx.x;
-    if (wg == 2 * nclasses) {
-        for (int c = tid; c < nclasses; c += blockDim.x) counts[c] = 0;
-        if (tid == 0) {
-            hdr->err = 0;
-            hdr->ticket = 0;
-            hdr->ntiles = 0;
-            hdr->grouped = grouped;
-        }
-        return;
-    }
-    const int dir = wg / nclasses;
-    const int c = wg % nclasses;
     const int n = 1 << log2n;
     const int half = n >> 1;
     const int passes = rounds * log2n;
-
-    __shared__ double scale[256];
-    __shared__ int any_bad;
     const size_t table = static_cast<size_t>(dir) * nclasses + c;
-    float* cbase = coef + table * passes * 2 * n;
-
-    // Attempt 0 builds the scaled schedule; if any scale factor leaves the
-    // safe range, attempt 1 rebuilds the table for the direct schedule.
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        const bool all_direct = attempt == 1;
-        for (int i = tid; i < n; i += blockDim.x) scale[i] = 1.0;
-        if (tid == 0) any_bad = 0;
+    float* cbase = coef + table * passes * n;
+    const int batch_passes = kAngleBatch / half;
+    for (int i = tid; i < n; i += blockDim.x) sh.t.sign[i] = 1;
+    for (int p0 = 0; p0 < passes; p0 += batch_passes) {
+        const int p1 = min(passes, p0 + batch_passes);
         __syncthreads();
-        for (int p = 0; p < passes; ++p) {
-            const int kk = p % log2n;
-            const int rr = p / log2n;
+        for (int e = tid; e < (p1 - p0) * half; e += blockDim.x) {
+            // Pass p in application order: the inverse runs the rounds and
+            // the passes backwards with negated angles (eq. (6), eq. (9)).
+            const int p = p0 + e / half;
+            const int j = e % half;
+            const int kk = p % log2n, rr = p / log2n;
             const int k = dir ? log2n - 1 - kk : kk;
             const int r = dir ? rounds - 1 - rr : rr;
-            const bool direct = all_direct || p == passes - 1;
-            float* cp = cbase + static_cast<size_t>(p) * 2 * n;
+            double th = static_cast<double>(
+                angles[((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + j]);
+            if (dir) th = -th;
+            // G(th) = f * G(phi) with |phi| <= pi/2
+            const double pi = 3.141592653589793238462643383279502884;
+            double phi = th;
+            signed char f = 1;
+            if (phi > pi / 2) { phi -= pi; f = -1; }
+            else if (phi < -pi / 2) { phi += pi; f = -1; }
+            sh.t.tanh_phi[e] = static_cast<float>(tan(0.5 * phi));
+            sh.t.sin_phi[e] = static_cast<float>(sin(phi));
+            sh.t.flip[e] = f;
+        }
+        __syncthreads();
+        for (int p = p0; p < p1; ++p) {
+            const int kk = p % log2n;
+            const int k = dir ? log2n - 1 - kk : kk;
             if (tid < half) {
+                const int e = (p - p0) * half + tid;
                 const int m = insert_zero_bit(tid, k);
                 const int nn = m + (1 << k);
-                double th = static_cast<double>(
-                    angles[((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + tid]);
-                if (dir) th = -th;  // eq. (9): the inverse pass uses negated angles
-                double sn, cs;
-                sincos(th, &sn, &cs);
-                const double sm = scale[m];
-                const double sq = scale[nn];
-                if (direct) {
-                    cp[4 * tid + 0] = static_cast<float>(cs * sm);
-                    cp[4 * tid + 1] = static_cast<float>(sn * sq);
-                    cp[4 * tid + 2] = static_cast<float>(cs * sq);
-                    cp[4 * tid + 3] = static_cast<float>(-sn * sm);
-                    scale[m] = 1.0;
-                    scale[nn] = 1.0;
-                } else {
-                    const double nsm = cs * sm;
-                    const double nsq = cs * sq;
-                    const double lo = ldexp(1.0, -kScaleExp);
-                    // written so that NaN fails the test
-                    if (!(fabs(nsm) >= lo && fabs(nsq) >= lo)) any_bad = 1;
-                    cp[2 * tid + 0] = static_cast<float>(sn * sq / nsm);
-                    cp[2 * tid + 1] = static_cast<float>(-sn * sm / nsq);
-                    scale[m] = nsm;
-                    scale[nn] = nsq;
-                }
+                const int sm = sh.t.sign[m];
+                const int sq = sh.t.sign[nn];
+                const int f = sh.t.flip[e];
+                // a pair whose stored signs differ is rotated by -phi
+                const float g = sm == sq ? 1.0f : -1.0f;
+                float* cp = cbase + static_cast<size_t>(p) * n;
+                cp[2 * tid + 0] = g * sh.t.tanh_phi[e];
+                cp[2 * tid + 1] = -g * sh.t.sin_phi[e];
+                sh.t.sign[m] = f * sm;
+                sh.t.sign[nn] = sm == sq ? f * sm : -f * sm;
             }
             __syncthreads();
         }
-        if (!any_bad) {
-            if (tid == 0) modes[table] = all_direct ? 1 : 0;
-            return;
-        }
-        __syncthreads();
     }
+    int neg = 0;
+    for (int i = tid; i < n; i += blockDim.x) {
+        signs[table * n + i] = static_cast<float>(sh.t.sign[i]);
+        neg |= sh.t.sign[i] < 0;
+    }
+    neg = __syncthreads_or(neg);
+    if (tid == 0) modes[table] = neg ? 1 : 0;
 }
 
-// Block-wide exclusive scan of one int per thread (kPlanThreads threads).
+// Tiles of a class of `count` blocks: whole tiles of 64, rounded up to a
+// multiple of the tiles a rotation wavefront takes at once.
+__device__ __forceinline__ int class_tiles(int count) {
+    const int t = (count + kTile - 1) / kTile;
+    return (t + kTilesPerWave - 1) / kTilesPerWave * kTilesPerWave;
+}
+
+// Exclusive scan of one int per thread over the workgroup; returns the
+// thread's prefix and sets *total.
 __device__ int block_exclusive_scan(int v, int* sh, int* total) {
     const int tid = threadIdx.x;
     sh[tid] = v;
     __syncthreads();
-    for (int off = 1; off < kPlanThreads; off <<= 1) {
-        int add = tid >= off ? sh[tid - off] : 0;
+    for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
+        const int add = tid >= off ? sh[tid - off] : 0;
         __syncthreads();
         sh[tid] += add;
         __syncthreads();
     }
     const int incl = sh[tid];
-    *total = sh[kPlanThreads - 1];
+    *total = sh[blockDim.x - 1];
     __syncthreads();
     return incl - v;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void plan_hist_kernel(
-    const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, PlanHeader* __restrict__ hdr,
-    int32_t* __restrict__ counts, int32_t* __restrict__ cursor,
-    int32_t* __restrict__ class_start, int32_t* __restrict__ tile_start) {
-    __shared__ int hist[4096];
-    __shared__ int bad;
-    __shared__ int last;
-    __shared__ int scan_sh[kPlanThreads];
+// Class counts of chunk k -> counts[k][c]; out-of-range classes set
+// chunk_err[k]. Without class indices every block is class 0.
+__device__ void count_chunk(PlanShared& sh, int64_t k, const int32_t* __restrict__ cls,
+                            int64_t nblocks, int64_t chunk, int nclasses,
+                            int32_t* __restrict__ counts, int32_t* __restrict__ chunk_err) {
     const int tid = threadIdx.x;
-    for (int c = tid; c < nclasses; c += kPlanThreads) hist[c] = 0;
-    if (tid == 0) bad = 0;
+    const int64_t start = k * chunk;
+    const int cnt = static_cast<int>(min<int64_t>(chunk, nblocks - start));
+    for (int c = tid; c < nclasses; c += blockDim.x) sh.c.hist[c] = 0;
+    if (tid == 0) sh.flag = 0;
     __syncthreads();
-    const int64_t start = static_cast<int64_t>(blockIdx.x) * kChunk;
-    const int64_t stop = min(start + kChunk, nblocks);
-    for (int64_t i = start + tid; i < stop; i += kPlanThreads) {
-        const int c = cls[i];
-        if (c >= 0 && c < nclasses)
-            atomicAdd(&hist[c], 1);
-        else
-            bad = 1;
+    if (cls != nullptr) {
+        for (int i = tid; i < cnt; i += blockDim.x) {
+            const int c = cls[start + i];
+            if (c >= 0 && c < nclasses)
+                atomicAdd(&sh.c.hist[c], 1);
+            else
+                sh.flag = 1;
+        }
+    } else if (tid == 0) {
+        sh.c.hist[0] = cnt;
     }
     __syncthreads();
-    for (int c = tid; c < nclasses; c += kPlanThreads)
-        if (hist[c]) atomicAdd(&counts[c], hist[c]);
-    if (tid == 0 && bad) atomicOr(&hdr->err, 1);
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = atomicAdd(&hdr->ticket, 1) == static_cast<int>(gridDim.x) - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // Exclusive scans of the class counts and of the tiles per class. Each
-    // thread owns a contiguous run of classes.
-    const int per = (nclasses + kPlanThreads - 1) / kPlanThreads;
-    const int c0 = min(tid * per, nclasses);
-    const int c1 = min(c0 + per, nclasses);
-    int run_blocks = 0, run_tiles = 0;
-    for (int c = c0; c < c1; ++c) {
-        const int cnt = __hip_atomic_load(&counts[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        run_blocks += cnt;
-        run_tiles += (cnt + kTile - 1) / kTile;
-    }
-    int total_blocks = 0, total_tiles = 0;
-    int b = block_exclusive_scan(run_blocks, scan_sh, &total_blocks);
-    int t = block_exclusive_scan(run_tiles, scan_sh, &total_tiles);
-    for (int c = c0; c < c1; ++c) {
-        const int cnt = __hip_atomic_load(&counts[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        class_start[c] = b;
-        cursor[c] = b;
-        tile_start[c] = t;
-        b += cnt;
-        t += (cnt + kTile - 1) / kTile;
-    }
-    if (tid == 0) {
-        class_start[nclasses] = total_blocks;
-        tile_start[nclasses] = total_tiles;
-        hdr->ntiles = total_tiles;
-        hdr->ticket = 0;
-    }
+    for (int c = tid; c < nclasses; c += blockDim.x)
+        counts[k * nclasses + c] = sh.c.hist[c];
+    if (tid == 0) chunk_err[k] = sh.flag;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void plan_scatter_kernel(
-    const int32_t* __restrict__ cls, int64_t nblocks, int nclasses,
-    const PlanHeader* __restrict__ hdr, int32_t* __restrict__ cursor,
-    const int32_t* __restrict__ class_start, const int32_t* __restrict__ tile_start,
-    int4* __restrict__ tiles, int32_t* __restrict__ perm, int64_t max_tiles) {
-    __shared__ int hist[4096];
-    __shared__ int base[4096];
-    __shared__ int chunk_cls[kChunk];
+// Launch A: workgroups [0, 2C) build the multiplier tables of (direction,
+// class), the next nchunks workgroups count one chunk each.
+__global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(
+    const int32_t* __restrict__ cls, int64_t nblocks, const float* __restrict__ angles,
+    int log2n, int rounds, int nclasses, int64_t nchunks, int64_t chunk,
+    PlanHeader* __restrict__ hdr, int32_t* __restrict__ chunk_err,
+    int32_t* __restrict__ counts, int32_t* __restrict__ modes, float* __restrict__ coef,
+    float* __restrict__ signs) {
+    __shared__ PlanShared sh;
+    const int64_t wg = blockIdx.x;
+    if (wg < 2 * nclasses) {
+        build_table(sh, static_cast<int>(wg / nclasses), static_cast<int>(wg % nclasses), angles,
+                    log2n, rounds, nclasses, coef, signs, modes);
+        return;
+    }
+    const int64_t k = wg - 2 * nclasses;
+    if (k == 0 && threadIdx.x == 0) hdr->nchunks = static_cast<int32_t>(nchunks);
+    count_chunk(sh, k, cls, nblocks, chunk, nclasses, counts, chunk_err);
+}
+
+// Launch B: chunk k places its blocks. Class c's blocks fill tiles
+// tile_base[c] .. in chunk order; inside a chunk their order is that of the
+// LDS counters (any order gives the same results, block by block).
+__global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
+    const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
+    int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
+    int32_t* __restrict__ tile_class, int32_t* __restrict__ perm) {
+    __shared__ PlanShared sh;
     const int tid = threadIdx.x;
-    for (int c = tid; c < nclasses; c += kPlanThreads) hist[c] = 0;
+    const int64_t k = blockIdx.x;
+    const int64_t ncounts = nchunks * nclasses;
+    const bool cached = ncounts <= kCountsCache;
+    if (cached)
+        for (int64_t e = tid; e < ncounts; e += blockDim.x) sh.p.counts[e] = counts[e];
     __syncthreads();
-    const int64_t start = static_cast<int64_t>(blockIdx.x) * kChunk;
-    const int64_t stop = min(start + kChunk, nblocks);
-    for (int64_t i = start + tid; i < stop; i += kPlanThreads) {
-        const int c = cls[i];
-        chunk_cls[i - start] = c;
-        if (c >= 0 && c < nclasses) atomicAdd(&hist[c], 1);
+    for (int c = tid; c < nclasses; c += blockDim.x) {
+        int total = 0, pre = 0;
+        for (int64_t q = 0; q < nchunks; ++q) {
+            const int v = cached ? sh.p.counts[q * nclasses + c] : counts[q * nclasses + c];
+            total += v;
+            if (q < k) pre += v;
+        }
+        sh.p.total[c] = total;
+        sh.p.pre[c] = pre;
+        sh.p.pos[c] = 0;
     }
     __syncthreads();
-    for (int c = tid; c < nclasses; c += kPlanThreads) {
-        const int h = hist[c];
-        base[c] = h ? atomicAdd(&cursor[c], h) : 0;
-        hist[c] = 0;
+    // First tile of each class: exclusive scan of the per-class tile counts,
+    // each thread owning a contiguous run of classes.
+    const int per = (nclasses + blockDim.x - 1) / blockDim.x;
+    const int c0 = min(tid * per, nclasses);
+    const int c1 = min(c0 + per, nclasses);
+    int run = 0;
+    for (int c = c0; c < c1; ++c) run += class_tiles(sh.p.total[c]);
+    int ntiles = 0;
+    int base = block_exclusive_scan(run, sh.p.scan, &ntiles);
+    for (int c = c0; c < c1; ++c) {
+        sh.p.tile_base[c] = base;
+        base += class_tiles(sh.p.total[c]);
     }
+    if (tid == 0) sh.p.tile_base[nclasses] = ntiles;
     __syncthreads();
-    for (int64_t i = start + tid; i < stop; i += kPlanThreads) {
-        const int c = chunk_cls[i - start];
+    // Block ids of this chunk into their classes' tiles.
+    const int64_t start = k * chunk;
+    const int cnt = static_cast<int>(min<int64_t>(chunk, nblocks - start));
+    for (int i = tid; i < cnt; i += blockDim.x) {
+        const int c = cls != nullptr ? cls[start + i] : 0;
         if (c >= 0 && c < nclasses) {
-            const int pos = atomicAdd(&hist[c], 1);
-            perm[base[c] + pos] = static_cast<int32_t>(i);
+            const int p = sh.p.pre[c] + atomicAdd(&sh.p.pos[c], 1);
+            perm[static_cast<int64_t>(sh.p.tile_base[c]) * kTile + p] =
+                static_cast<int32_t>(start + i);
         }
     }
-    // Tile descriptors: this workgroup's share of the tile list.
-    const int ntiles = hdr->ntiles;
-    const int64_t per = (max_tiles + gridDim.x - 1) / gridDim.x;
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * per;
-    const int64_t t1 = min(t0 + per, static_cast<int64_t>(ntiles));
-    for (int64_t t = t0 + tid; t < t1; t += kPlanThreads) {
-        // last class whose first tile is <= t (classes with no tiles share
-        // their first tile with the next class, so take the last match)
+    // Class of every tile of this chunk's share of the tile list, and the
+    // empty lanes of each class's last tile.
+    const int64_t share = (max_tiles + nchunks - 1) / nchunks;
+    const int64_t t0 = k * share;
+    const int64_t t1 = min(t0 + share, max_tiles);
+    for (int64_t t = t0 + tid; t < t1; t += blockDim.x) {
+        if (t >= ntiles) {
+            tile_class[t] = -1;
+            continue;
+        }
+        // last class whose first tile is <= t (classes without blocks share
+        // their first tile index with the next class)
         int lo = 0, hi = nclasses - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+            if (sh.p.tile_base[mid] <= t) lo = mid; else hi = mid - 1;
         }
-        const int c = lo;
-        const int first = class_start[c] + static_cast<int>(t - tile_start[c]) * kTile;
-        const int count = min(kTile, class_start[c + 1] - first);
-        tiles[t] = make_int4(c, first, count, 0);
+        tile_class[t] = lo;
+        const int used = sh.p.total[lo] - static_cast<int>(t - sh.p.tile_base[lo]) * kTile;
+        for (int s2 = max(used, 0); s2 < kTile; ++s2) perm[t * kTile + s2] = -1;
     }
 }
 
@@ -258,20 +293,15 @@ __global__ __launch_bounds__(kPlanThreads) void plan_scatter_kernel(
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
                        const float* angles, int nclasses, const WsLayout& l,
                        const WsPtrs& p, hipStream_t stream) {
-    const int grouped = cls != nullptr ? 1 : 0;
-    hipLaunchKernelGGL(plan_tables_kernel, dim3(2 * nclasses + 1), dim3(kTableThreads), 0,
-                       stream, angles, log2n, rounds, nclasses, grouped, p.coef, p.modes,
-                       p.hdr, p.counts);
+    hipLaunchKernelGGL(plan_count_kernel, dim3(static_cast<unsigned>(2 * nclasses + l.nchunks)),
+                       dim3(kPlanThreads), 0, stream, cls, nblocks, angles, log2n, rounds,
+                       nclasses, l.nchunks, l.chunk, p.hdr, p.chunk_err, p.counts, p.modes,
+                       p.coef, p.signs);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !grouped || nblocks == 0) return e;
-    const dim3 grid(static_cast<unsigned>(l.nhist));
-    hipLaunchKernelGGL(plan_hist_kernel, grid, dim3(kPlanThreads), 0, stream, cls, nblocks,
-                       nclasses, p.hdr, p.counts, p.cursor, p.class_start, p.tile_start);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(plan_scatter_kernel, grid, dim3(kPlanThreads), 0, stream, cls, nblocks,
-                       nclasses, p.hdr, p.cursor, p.class_start, p.tile_start, p.tiles,
-                       p.perm, l.max_tiles);
+    hipLaunchKernelGGL(plan_place_kernel, dim3(static_cast<unsigned>(l.nchunks)),
+                       dim3(kPlanThreads), 0, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
+                       l.max_tiles, p.counts, p.tile_class, p.perm);
     return hipGetLastError();
 }
 

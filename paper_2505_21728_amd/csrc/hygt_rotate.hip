@@ -8,25 +8,46 @@
 // are wave-uniform, so they arrive through scalar loads as SGPR operands of
 // the FMAs. Nothing is exchanged between lanes during the passes.
 //
-// Memory. A tile's blocks are moved between HBM and registers through LDS
-// so that every global access covers whole 256-byte blocks: each load
-// instruction fetches 16 bytes per lane for 64/(N/4) blocks, with the 16-byte
-// chunks of a block rotated by an XOR swizzle so that the per-lane row reads
-// (and the mirror-image writes on the way out) hit distinct LDS banks. Loads
-// go straight to LDS (global_load_lds_dwordx4) without passing through VGPRs.
+// Memory. A tile moves between HBM and registers through LDS in both
+// directions, so that every global access covers whole blocks (or whole
+// 128-byte halves of 8x8 blocks): each load or store instruction moves 16
+// bytes per lane for several blocks. The 16-byte chunks of a block are
+// rotated by an XOR swizzle in LDS so that the per-lane row reads and writes
+// hit distinct banks. Loads go straight to LDS (global_load_lds_dwordx4)
+// without passing through VGPRs. A tile goes through in parts of at most 8
+// chunks per block, so a wavefront needs only 8 KB of LDS.
 //
-// Arithmetic. A class's transform runs either in the scaled schedule (every
-// pass but the last as two FMAs per butterfly, the last pass direct) or, when
-// its angles would drive the scale factors out of range, in the direct
-// schedule (a multiply and an FMA per output everywhere); the plan picks the
-// schedule from the angles alone (see hygt_plan.hip). Every operation is an
-// explicit fmaf or a single multiply, so every block of a class sees the same
-// rounding whatever the batch, tile or launch.
+// Scheduling. Each wavefront handles one tile, four per workgroup. The
+// lifting form needs no temporaries, so a wavefront fits in under 100 VGPRs
+// and five wavefronts per SIMD stay resident: measured on MI355X, raising
+// residency from two to five wavefronts per SIMD cut the 8x8 forward
+// transform from 177 to 144 us, because loads, rotations and stores of
+// different tiles then overlap. Tiles are sorted by class (see
+// hygt_plan.hip) and each XCD walks its own contiguous share of the tile
+// list, so the wavefronts that share a scalar cache mostly read one class
+// table: measured on MI355X, the rotation slows by about a third once a
+// compute-unit pair's wavefronts touch more than about three tables.
+//
+// Arithmetic. Each pair is rotated with the three in-place lifting steps
+// built by the plan (see hygt_plan.hip), and a class whose sign bookkeeping
+// left negative outputs multiplies them by -1 at the end. Every operation is
+// an explicit fmaf or an exact sign flip, so every block of a class sees the
+// same rounding whatever the batch, tile or launch.
 
 #include "hygt_internal.h"
 
 namespace hygt {
 namespace {
+
+// Wavefronts (tiles) per workgroup of the rotation kernels.
+constexpr int kWaves = 4;
+// Accelerator complex dies (XCDs) that workgroups are dispatched over.
+constexpr int kXcds = 8;
+// Register budget of the rotation kernels: resident wavefronts per SIMD.
+#ifndef HYGT_WAVES_PER_SIMD
+#define HYGT_WAVES_PER_SIMD 5
+#endif
+constexpr int kWavesPerSimd = HYGT_WAVES_PER_SIMD;
 
 template <int I, int End>
 struct StaticFor {
@@ -55,68 +76,40 @@ __device__ __forceinline__ int swz(int b) {
     else return 0;
 }
 
-// One scaled pass along hypercube dimension K.
-template <int D, int K>
-__device__ __forceinline__ void pass_scaled(float (&v)[1 << D], const float* __restrict__ cp) {
+// The passes act on T blocks at once (one per tile of the wavefront, all of
+// one class): every multiplier fetched is used by T blocks.
+
+// One pass along hypercube dimension K: each pair (m, n) gets the lifting
+// steps a += p b, b += q a, a += p b, in place (three FMAs, no temporary).
+template <int D, int K, int T>
+__device__ __forceinline__ void pass_lift(float (&v)[T][1 << D], const float* __restrict__ cp) {
     StaticFor<0, (1 << D) / 2>::run([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         constexpr int m = ins0(j, K);
         constexpr int n = m + (1 << K);
-        const float a = v[m];
-        const float b = v[n];
-        v[m] = fmaf(cp[2 * j], b, a);
-        v[n] = fmaf(cp[2 * j + 1], a, b);
-    });
-}
-
-// One direct pass along hypercube dimension K.
-template <int D, int K>
-__device__ __forceinline__ void pass_direct(float (&v)[1 << D], const float* __restrict__ cp) {
-    StaticFor<0, (1 << D) / 2>::run([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        constexpr int m = ins0(j, K);
-        constexpr int n = m + (1 << K);
-        const float a = v[m];
-        const float b = v[n];
-        v[m] = fmaf(cp[4 * j], a, cp[4 * j + 1] * b);
-        v[n] = fmaf(cp[4 * j + 2], b, cp[4 * j + 3] * a);
-    });
-}
-
-// All passes but the last in the scaled form, the last direct. RT > 0 unrolls
-// the R rounds at compile time (RT == R); RT == 0 loops over `rounds`.
-template <int D, int DIR, int RT>
-__device__ __forceinline__ void run_scaled_schedule(float (&v)[1 << D], const float* __restrict__ tbl,
-                                                    int rounds) {
-    constexpr int N = 1 << D;
-    auto one_round = [&](int r, auto last_round) {
-        StaticFor<0, D>::run([&](auto kk) {
-            constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
-            const float* cp = tbl + static_cast<size_t>(r * D + decltype(kk)::value) * 2 * N;
-            if constexpr (decltype(last_round)::value && decltype(kk)::value == D - 1)
-                pass_direct<D, K>(v, cp);
-            else
-                pass_scaled<D, K>(v, cp);
+        const float p = cp[2 * j];
+        const float q = cp[2 * j + 1];
+        StaticFor<0, T>::run([&](auto uu) {
+            constexpr int u = decltype(uu)::value;
+            v[u][m] = fmaf(p, v[u][n], v[u][m]);
+            v[u][n] = fmaf(q, v[u][m], v[u][n]);
+            v[u][m] = fmaf(p, v[u][n], v[u][m]);
         });
-    };
-    if constexpr (RT > 0) {
-        StaticFor<0, RT - 1>::run([&](auto rr) { one_round(decltype(rr)::value, std::false_type{}); });
-        one_round(RT - 1, std::true_type{});
-    } else {
-        for (int r = 0; r < rounds - 1; ++r) one_round(r, std::false_type{});
-        one_round(rounds - 1, std::true_type{});
-    }
+    });
 }
 
-// Every pass direct (classes whose scaled schedule would leave the safe range).
-template <int D, int DIR, int RT>
-__device__ __forceinline__ void run_direct_schedule(float (&v)[1 << D], const float* __restrict__ tbl,
-                                                    int rounds) {
+// R rounds of D passes in application order (forward: k = 0..D-1 in every
+// round; inverse: k = D-1..0), then the final signs. RT > 0 unrolls the
+// rounds at compile time (RT == R); RT == 0 loops over `rounds`.
+template <int D, int DIR, int RT, int T>
+__device__ __forceinline__ void run_passes(float (&v)[T][1 << D], const float* __restrict__ tbl,
+                                           const float* __restrict__ sign, int has_neg,
+                                           int rounds) {
     constexpr int N = 1 << D;
     auto one_round = [&](int r) {
         StaticFor<0, D>::run([&](auto kk) {
             constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
-            pass_direct<D, K>(v, tbl + static_cast<size_t>(r * D + decltype(kk)::value) * 2 * N);
+            pass_lift<D, K, T>(v, tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N);
         });
     };
     if constexpr (RT > 0) {
@@ -124,146 +117,240 @@ __device__ __forceinline__ void run_direct_schedule(float (&v)[1 << D], const fl
     } else {
         for (int r = 0; r < rounds; ++r) one_round(r);
     }
+    if (has_neg) {
+        StaticFor<0, N>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const float sg = sign[i];
+            StaticFor<0, T>::run([&](auto uu) { v[decltype(uu)::value][i] *= sg; });
+        });
+    }
 }
 
-template <int D, int DIR, int RT>
-__device__ __forceinline__ void run_passes(float (&v)[1 << D], const float* __restrict__ tbl,
-                                           int direct_mode, int rounds) {
-    if (direct_mode)
-        run_direct_schedule<D, DIR, RT>(v, tbl, rounds);
-    else
-        run_scaled_schedule<D, DIR, RT>(v, tbl, rounds);
+__device__ __forceinline__ int valid_block(int b, int64_t nblocks) {
+    return (b >= 0 && b < nblocks) ? b : -1;  // never touch memory outside x / y
 }
 
-struct TileInfo {
-    int cls;
-    int count;
-    int64_t first;
-    bool valid;
+// A tile moves between HBM and LDS in PARTS parts of CHP 16-byte chunks per
+// block (CHP = min(N/4, kChunksPerPart)); a wavefront's LDS image of one part
+// is 64 * CHP * 16 bytes.
+#ifndef HYGT_CHUNKS_PER_PART
+#define HYGT_CHUNKS_PER_PART 8
+#endif
+constexpr int kChunksPerPart = HYGT_CHUNKS_PER_PART;
+template <int D>
+struct TileGeo {
+    static constexpr int N = 1 << D;
+    static constexpr int CH = N / 4;                 // 16-byte chunks per block
+    static constexpr int CHP = CH < kChunksPerPart ? CH : kChunksPerPart;  // per part
+    static constexpr int PARTS = CH / CHP;
+    static constexpr int BPI = 64 / CHP;             // blocks per memory instruction
 };
 
-__device__ __forceinline__ TileInfo tile_info(int64_t tile, const PlanHeader* __restrict__ hdr,
-                                              const int4* __restrict__ tiles, int64_t nblocks) {
-    TileInfo t{0, 0, 0, false};
-    if (hdr->grouped) {
-        if (tile >= hdr->ntiles) return t;
-        const int4 d = tiles[tile];
-        t.cls = __builtin_amdgcn_readfirstlane(d.x);
-        t.first = __builtin_amdgcn_readfirstlane(d.y);
-        t.count = __builtin_amdgcn_readfirstlane(d.z);
-    } else {
-        t.first = tile * kTile;
-        if (t.first >= nblocks) return t;
-        t.count = static_cast<int>(min<int64_t>(kTile, nblocks - t.first));
-    }
-    t.valid = true;
-    return t;
+// Block id handled by memory instruction i of every part: block
+// b = i*BPI + lane/CHP of the tile.
+template <int D>
+__device__ __forceinline__ void instr_blocks(int* bb, int blk, int lane) {
+    using G = TileGeo<D>;
+    StaticFor<0, G::CHP>::run([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        bb[i] = __builtin_amdgcn_ds_bpermute((i * G::BPI + lane / G::CHP) << 2, blk);
+    });
 }
 
-// N >= 4: LDS-staged tile, one lane per block.
+// Instruction i of part `part` fetches, for block b = i*BPI + lane/CHP, the chunk
+// part*CHP + ((lane%CHP) ^ swz(b)) into LDS slot i*64 + lane, which is
+// b*CHP + (chunk-in-part ^ swz(b)).
+template <int D>
+__device__ __forceinline__ void gather_part(const float* __restrict__ x, float4* L,
+                                            const int* bb, int lane, int part) {
+    using G = TileGeo<D>;
+    StaticFor<0, G::CHP>::run([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const int b = i * G::BPI + lane / G::CHP;
+        const int ch = part * G::CHP + ((lane % G::CHP) ^ swz<G::CHP>(b));
+#if defined(__HIP_DEVICE_COMPILE__)  // the LDS-DMA builtin exists only in the device pass
+        if (bb[i] >= 0)
+            __builtin_amdgcn_global_load_lds(x + static_cast<int64_t>(bb[i]) * G::N + ch * 4,
+                                             (lds_void_ptr)(L + i * 64), 16, 0, 0);
+#else
+        (void)b, (void)ch, (void)x, (void)L;
+#endif
+    });
+}
+
+template <int D>
+__device__ __forceinline__ void scatter_part(float* __restrict__ y, const float4* L,
+                                             const int* bb, int lane, int part) {
+    using G = TileGeo<D>;
+    StaticFor<0, G::CHP>::run([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const int b = i * G::BPI + lane / G::CHP;
+        const int ch = part * G::CHP + ((lane % G::CHP) ^ swz<G::CHP>(b));
+        const float4 f = L[i * 64 + lane];
+        if (bb[i] >= 0)
+            *reinterpret_cast<float4*>(y + static_cast<int64_t>(bb[i]) * G::N + ch * 4) = f;
+    });
+}
+
+// Brings part P of a tile into registers: gather into L, then each lane
+// reads its block's CHP chunks of the part.
+template <int D, int P>
+__device__ __forceinline__ void load_part(const float* __restrict__ x, float4* L, const int* bb,
+                                          float* v, int lane, int sw) {
+    using G = TileGeo<D>;
+    constexpr int CHP = G::CHP;
+    gather_part<D>(x, L, bb, lane, P);
+    // The DMA writes land in LDS asynchronously.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    StaticFor<0, CHP>::run([&](auto qq) {
+        constexpr int q = decltype(qq)::value;
+        constexpr int e = 4 * (P * CHP + q);
+        const float4 f = L[lane * CHP + (q ^ sw)];
+        v[e + 0] = f.x;
+        v[e + 1] = f.y;
+        v[e + 2] = f.z;
+        v[e + 3] = f.w;
+    });
+    // A later DMA into L must not overtake these row reads.
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Writes part P of a tile back: each lane writes its block's CHP chunks of
+// the part into L, then the transposed slots go out as whole blocks.
+template <int D, int P>
+__device__ __forceinline__ void store_part(float* __restrict__ y, float4* L, const int* bb,
+                                           const float* v, int lane, int sw) {
+    using G = TileGeo<D>;
+    constexpr int CHP = G::CHP;
+    StaticFor<0, CHP>::run([&](auto qq) {
+        constexpr int q = decltype(qq)::value;
+        constexpr int e = 4 * (P * CHP + q);
+        L[lane * CHP + (q ^ sw)] = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    });
+    // LDS executes one wavefront's operations in order; only the compiler's
+    // ordering of the transposed reads after the row writes needs pinning.
+    asm volatile("" ::: "memory");
+    scatter_part<D>(y, L, bb, lane, P);
+    // Later row writes into L must not overtake the transposed reads.
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Tiles of workgroup w: workgroups are dispatched round-robin over the
+// XCDs (w mod 8), so workgroup w takes the (w / 8)-th group of tiles of
+// XCD (w mod 8)'s contiguous share of the class-sorted tile list. The waves
+// that share an XCD's scalar caches then work on one or two classes at a
+// time. The grid is a multiple of 8 workgroups.
+__device__ __forceinline__ int64_t xcd_tile_group() {
+    const int64_t w = blockIdx.x;
+    const int64_t per_xcd = gridDim.x / kXcds;
+    return (w % kXcds) * per_xcd + w / kXcds;
+}
+
+// N >= 4: LDS-staged tiles, one lane per block, one tile per wavefront.
+//
+// x and y may be the same array (in place): every block is read by the
+// wavefront that owns it and written back only after that read has
+// completed, and no other wavefront touches it, so the restrict qualifiers
+// (which let the per-tile class loads stay scalar) hold for every pair of
+// accesses that the compiler could reorder.
 template <int D, int DIR, int RT>
-__global__ __launch_bounds__(256) void rotate_kernel(
-    const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
-    const PlanHeader* __restrict__ hdr, const int4* __restrict__ tiles,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ modes,
-    const float* __restrict__ coef) {
-    constexpr int N = 1 << D;
-    constexpr int CH = N / 4;       // 16-byte chunks per block
-    constexpr int BPI = 64 / CH;    // blocks per load instruction
-    __shared__ float4 lds[4][kTile * CH];
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd)))
+void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t nblocks,
+                   int rounds, int nclasses, int64_t max_tiles,
+                   const int32_t* __restrict__ tile_class, const int32_t* __restrict__ perm,
+                   const int32_t* __restrict__ modes, const float* __restrict__ coef,
+                   const float* __restrict__ signs) {
+    using G = TileGeo<D>;
+    constexpr int N = G::N;
+    constexpr int CHP = G::CHP;
+    constexpr int T = kTilesPerWave;
+    __shared__ float4 lds[kWaves][kTile * CHP];
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wv;
-    const TileInfo ti = tile_info(tile, hdr, tiles, nblocks);
-    if (!ti.valid) return;
-
-    int blk = -1;
-    if (lane < ti.count && ti.first + lane < nblocks) {
-        blk = hdr->grouped ? perm[ti.first + lane] : static_cast<int>(ti.first + lane);
-        if (blk < 0 || blk >= nblocks) blk = -1;  // never touch memory outside x / y
+    // This wavefront's T consecutive tiles; the plan gives them one class.
+    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * T;
+    if (t0 >= max_tiles) return;
+    const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
+    if (c < 0) return;  // past the last tile
+    float4* L = lds[wv];
+    int blk[T];
+    float v[T][N];
+    {
+        const int sw = swz<CHP>(lane);
+        StaticFor<0, T>::run([&](auto uu) {
+            constexpr int u = decltype(uu)::value;
+            blk[u] = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
+            int bb[CHP];
+            instr_blocks<D>(bb, blk[u], lane);
+            load_part<D, 0>(x, L, bb, v[u], lane, sw);
+            if constexpr (G::PARTS > 1) load_part<D, 1>(x, L, bb, v[u], lane, sw);
+        });
     }
 
-    float4* L = lds[wv];
-    // Gather: instruction i fetches chunk (lane%CH)^swz(b) of block b = i*BPI + lane/CH.
-    StaticFor<0, CH>::run([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        const int b = i * BPI + lane / CH;
-        const int bb = __builtin_amdgcn_ds_bpermute(b << 2, blk);
-        const int ch = (lane % CH) ^ swz<CH>(b);
-        if (bb >= 0)
-            __builtin_amdgcn_global_load_lds(x + static_cast<int64_t>(bb) * N + ch * 4,
-                                             (lds_void_ptr)(L + i * 64), 16, 0, 0);
-    });
-    // The DMA writes land in LDS asynchronously: wait for them before the
-    // row reads (the asm also keeps the compiler from hoisting those reads).
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-
-    float v[N];
-    const int sw = swz<CH>(lane);
-    StaticFor<0, CH>::run([&](auto qq) {
-        constexpr int q = decltype(qq)::value;
-        const float4 t = L[lane * CH + (q ^ sw)];
-        v[4 * q + 0] = t.x;
-        v[4 * q + 1] = t.y;
-        v[4 * q + 2] = t.z;
-        v[4 * q + 3] = t.w;
-    });
-
-    const size_t table = static_cast<size_t>(DIR) * nclasses + ti.cls;
     const size_t passes = static_cast<size_t>(rounds) * D;
-    run_passes<D, DIR, RT>(v, coef + table * passes * 2 * N, modes[table], rounds);
+    const size_t table = static_cast<size_t>(DIR) * nclasses + c;
+    run_passes<D, DIR, RT, T>(v, coef + table * passes * N, signs + table * N, modes[table],
+                              rounds);
 
-    StaticFor<0, CH>::run([&](auto qq) {
-        constexpr int q = decltype(qq)::value;
-        L[lane * CH + (q ^ sw)] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-    });
-    // Rows written by each lane are read back by other lanes of the same
-    // wavefront; LDS executes one wavefront's operations in order, so only the
-    // compiler's ordering needs pinning here.
-    asm volatile("" ::: "memory");
-    StaticFor<0, CH>::run([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        const int b = i * BPI + lane / CH;
-        const int bb = __builtin_amdgcn_ds_bpermute(b << 2, blk);
-        const int ch = (lane % CH) ^ swz<CH>(b);
-        const float4 t = L[i * 64 + lane];
-        if (bb >= 0) *reinterpret_cast<float4*>(y + static_cast<int64_t>(bb) * N + ch * 4) = t;
+    // Addresses for the way out are derived again from the block ids and the
+    // lane index, made opaque here so that the compiler does not keep the
+    // ones of the way in alive (in registers) across the passes.
+    int lane2 = lane;
+    asm volatile("" : "+v"(lane2));
+    const int sw2 = swz<CHP>(lane2);
+    StaticFor<0, T>::run([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        int b = blk[u];
+        asm volatile("" : "+v"(b));
+        int bb[CHP];
+        instr_blocks<D>(bb, b, lane2);
+        store_part<D, 0>(y, L, bb, v[u], lane2, sw2);
+        if constexpr (G::PARTS > 1) store_part<D, 1>(y, L, bb, v[u], lane2, sw2);
     });
 }
 
 // N == 2: one 8-byte block per lane, read and written directly.
 template <int DIR>
-__global__ __launch_bounds__(256) void rotate_kernel_n2(
-    const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
-    const PlanHeader* __restrict__ hdr, const int4* __restrict__ tiles,
+__global__ __launch_bounds__(64 * kWaves) void rotate_kernel_n2(
+    const float* __restrict__ x, float* __restrict__ y, int64_t nblocks, int rounds,
+    int nclasses, int64_t max_tiles, const int32_t* __restrict__ tile_class,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ modes,
-    const float* __restrict__ coef) {
+    const float* __restrict__ coef, const float* __restrict__ signs) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wv;
-    const TileInfo ti = tile_info(tile, hdr, tiles, nblocks);
-    if (!ti.valid) return;
-    if (lane >= ti.count || ti.first + lane >= nblocks) return;
-    const int blk = hdr->grouped ? perm[ti.first + lane] : static_cast<int>(ti.first + lane);
-    if (blk < 0 || blk >= nblocks) return;  // never touch memory outside x / y
-    const float2 in = *reinterpret_cast<const float2*>(x + static_cast<int64_t>(blk) * 2);
-    float v[2] = {in.x, in.y};
-    const size_t table = static_cast<size_t>(DIR) * nclasses + ti.cls;
-    run_passes<1, DIR, 0>(v, coef + table * rounds * 4, modes[table], rounds);
-    *reinterpret_cast<float2*>(y + static_cast<int64_t>(blk) * 2) = make_float2(v[0], v[1]);
+    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    if (t0 >= max_tiles) return;
+    const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
+    if (c < 0) return;
+    const size_t table = static_cast<size_t>(DIR) * nclasses + c;
+    for (int u = 0; u < kTilesPerWave; ++u) {
+        const int blk = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
+        if (blk < 0) continue;
+        const float2 in = *reinterpret_cast<const float2*>(x + static_cast<int64_t>(blk) * 2);
+        float v[1][2] = {{in.x, in.y}};
+        run_passes<1, DIR, 0, 1>(v, coef + table * rounds * 2, signs + table * 2, modes[table],
+                                 rounds);
+        *reinterpret_cast<float2*>(y + static_cast<int64_t>(blk) * 2) =
+            make_float2(v[0][0], v[0][1]);
+    }
 }
 
 template <int D, int DIR, int RT>
 hipError_t launch_one(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
                       const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
-    const dim3 grid(static_cast<unsigned>((l.max_tiles + 3) / 4));
+    const int64_t per_group = static_cast<int64_t>(kWaves) * kTilesPerWave;
+    const int64_t groups = (l.max_tiles + per_group - 1) / per_group;
+    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    const dim3 block(64 * kWaves);
     if constexpr (D == 1)
-        hipLaunchKernelGGL((rotate_kernel_n2<DIR>), grid, dim3(256), 0, stream, x, y, nblocks,
-                           rounds, nclasses, p.hdr, p.tiles, p.perm, p.modes, p.coef);
+        hipLaunchKernelGGL((rotate_kernel_n2<DIR>), grid, block, 0, stream, x, y, nblocks,
+                           rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes, p.coef,
+                           p.signs);
     else
-        hipLaunchKernelGGL((rotate_kernel<D, DIR, RT>), grid, dim3(256), 0, stream, x, y,
-                           nblocks, rounds, nclasses, p.hdr, p.tiles, p.perm, p.modes, p.coef);
+        hipLaunchKernelGGL((rotate_kernel<D, DIR, RT>), grid, block, 0, stream, x, y, nblocks,
+                           rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes,
+                           p.coef, p.signs);
     return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ def test_workspace_bytes():
     assert ws(4096, 4, 2, 1) >= 4096 * 4
     big = ws(1 << 20, 6, 4, 35)
     # grouping (perm 4 B/block + tiles) and tables for both directions
-    assert big >= (1 << 20) * 4 + 2 * 35 * 24 * 128 * 4
+    # grouping (4 B per block slot) and two FP32 multipliers per pair, both directions
+    assert big >= (1 << 20) * 4 + 2 * 35 * 24 * 64 * 4
     assert ws(1 << 20, 6, 4, 35) < ws(1 << 21, 6, 4, 35)
     for bad in [(-1, 4, 2, 1), (10, 0, 2, 1), (10, 9, 2, 1), (10, 4, 0, 1),
                 (10, 4, 65, 1), (10, 4, 2, 0), (10, 4, 2, 4097), (1 << 31, 4, 2, 1)]:
