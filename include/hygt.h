@@ -100,12 +100,16 @@ enum hygt_direction {
 size_t hygt_workspace_bytes(int64_t nblocks, int log2n, int rounds, int nclasses);
 
 /* Builds, in the workspace, everything that depends on the classes and the
- * angles but not on the data (one kernel launch):
- *   - the multiplier tables of both directions: cos and sin of every angle,
- *     evaluated in FP64 (the paper's "conversion to higher precision
- *     multipliers", Sec. IV) and folded into per-pass FP32 coefficients;
- *   - a grouping of the blocks by class into tiles of 64 blocks of one class
- *     (per chunk of 16384 consecutive blocks).
+ * angles but not on the data (two kernel launches):
+ *   - the multiplier tables of both directions: every angle converted in
+ *     FP64 into per-pass FP32 multipliers (Sec. IV keeps the parameters
+ *     compact and converts them to higher-precision multipliers when they
+ *     are used): the two multipliers of a three-step lifting form of each
+ *     rotation, or for N = 256 and the passes along bit 7, its cosine and
+ *     sine;
+ *   - the blocks sorted by class over the whole batch into tiles of 64
+ *     blocks of one class (a counting sort), with a flag for any class
+ *     index outside [0, nclasses).
  * cls is read; angles is read. Both may be reused or freed once the stream
  * reaches the end of this call's work. */
 int hygt_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,

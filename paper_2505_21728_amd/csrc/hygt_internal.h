@@ -23,6 +23,12 @@ constexpr int64_t kMinChunk = 4096;
 constexpr int64_t kMaxChunks = 1024;
 // Threads per plan workgroup (>= N/2 for the table builders, N <= 256).
 constexpr int kPlanThreads = 256;
+// Hypercube dimensions kept inside one wavefront lane: a lane holds at most
+// 128 values, so for N = 256 two wavefronts share each tile, one per half of
+// every block, and the passes along bit 7 pair values of different
+// wavefronts. Those passes use the plain (cos, sin) form of the rotation,
+// the others the lifting form (see hygt_plan.hip).
+constexpr int kLaneBits = 7;
 
 // Device-side header at the start of the workspace.
 struct alignas(256) PlanHeader {
@@ -37,7 +43,7 @@ struct WsLayout {
     size_t tile_class = 0;   // int32 [max_tiles] class of each tile, -1 past the last
     size_t perm = 0;         // int32 [max_tiles][64] block ids of each tile, -1 = empty lane
     size_t modes = 0;        // int32 [2][C] 1 = some output needs a final sign flip
-    size_t coef = 0;         // float [2][C][P][N] per-pass lifting multipliers (p, q per pair)
+    size_t coef = 0;         // float [2][C][P][N] per-pass multipliers (two per pair)
     size_t signs = 0;        // float [2][C][N] final sign (+1 / -1) of each output
     size_t total = 0;
     int64_t nchunks = 0;

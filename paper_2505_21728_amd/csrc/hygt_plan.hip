@@ -20,6 +20,12 @@
 // outputs. Both the reduction and the sign bookkeeping depend only on the
 // angles, so every block of a class follows the same arithmetic.
 //
+// For N = 256 the passes along bit 7 pair values held by two wavefronts,
+// which exchange them through LDS, and each side computes its own output
+// from both inputs: those passes store (cos theta, sin theta) rather than
+// lifting multipliers, with the sine's sign adjusted for the stored signs of
+// the pair (the signs themselves are left unchanged by such a pass).
+//
 // Grouping. A tile is 64 blocks of one class, so that a wavefront (one lane
 // per block) reads one class table with scalar loads. Tiles are sorted by
 // class over the whole batch, so that the wavefronts of a compute unit pair
@@ -32,6 +38,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "hygt.h"
 #include "hygt_internal.h"
 
 namespace hygt {
@@ -46,34 +53,64 @@ __device__ __forceinline__ int insert_zero_bit(int j, int k) {
 constexpr int kAngleBatch = 2048;
 // Entries of the per-chunk class counts cached in LDS by the placing kernel.
 constexpr int kCountsCache = 16384;
+// Blocks whose class indices one thread loads at once.
+constexpr int kUnroll = 4;
 
-struct PlanShared {
+// LDS of the first plan launch: a table builder or a chunk counter.
+struct CountShared {
     union {
         struct {  // table builders
             int sign[256];
-            float tanh_phi[kAngleBatch];  // tan(phi/2) of the batch's angles
-            float sin_phi[kAngleBatch];   // sin(phi)
+            float tanh_phi[kAngleBatch];  // tan(phi/2) of the batch's angles (cos for bit 7)
+            float sin_phi[kAngleBatch];   // sin(phi) (sin theta for bit 7)
             signed char flip[kAngleBatch];  // -1 where |theta| > pi/2
         } t;
         struct {  // chunk counting
-            int hist[4096];
+            int hist[HYGT_MAX_CLASSES];
         } c;
-        struct {  // chunk placing
-            int counts[kCountsCache];
-            int total[4096];      // blocks of each class in the batch
-            int pre[4096];        // blocks of each class in earlier chunks
-            int tile_base[4097];  // first tile of each class
-            int pos[4096];        // blocks of each class placed by this chunk so far
-            int scan[kPlanThreads];
-        } p;
     };
     int flag;
 };
 
+// LDS of the placing launch, sized at launch time for the class count:
+// the cached per-chunk counts (when they fit), then per class the blocks in
+// the batch, the blocks in earlier chunks, the blocks placed so far and the
+// first tile, then the scan scratch.
+struct PlaceLds {
+    int* counts;
+    int* total;
+    int* pre;
+    int* pos;
+    int* tile_base;  // [C + 1]
+    int* scan;       // [kPlanThreads]
+};
+
+__host__ __device__ inline bool place_counts_cached(int64_t nchunks, int nclasses) {
+    return nchunks * nclasses <= kCountsCache;
+}
+
+__host__ __device__ inline size_t place_lds_bytes(int64_t nchunks, int nclasses) {
+    const size_t cached = place_counts_cached(nchunks, nclasses)
+                              ? static_cast<size_t>(nchunks) * nclasses : 0;
+    return (cached + 4 * static_cast<size_t>(nclasses) + 1 + kPlanThreads) * sizeof(int);
+}
+
+__device__ inline PlaceLds place_lds(int* base, int64_t nchunks, int nclasses) {
+    PlaceLds l;
+    l.counts = base;
+    int* p = base + (place_counts_cached(nchunks, nclasses) ? nchunks * nclasses : 0);
+    l.total = p;
+    l.pre = p + nclasses;
+    l.pos = p + 2 * nclasses;
+    l.tile_base = p + 3 * nclasses;
+    l.scan = p + 4 * nclasses + 1;
+    return l;
+}
+
 // Multiplier table of one (direction, class); see the file comment. The
 // FP64 conversion of a batch of angles runs in parallel; only the sign walk
 // through the passes is sequential.
-__device__ void build_table(PlanShared& sh, int dir, int c, const float* __restrict__ angles,
+__device__ void build_table(CountShared& sh, int dir, int c, const float* __restrict__ angles,
                             int log2n, int rounds, int nclasses, float* __restrict__ coef,
                             float* __restrict__ signs, int32_t* __restrict__ modes) {
     const int tid = threadIdx.x;
@@ -98,6 +135,12 @@ __device__ void build_table(PlanShared& sh, int dir, int c, const float* __restr
             double th = static_cast<double>(
                 angles[((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + j]);
             if (dir) th = -th;
+            if (k >= kLaneBits) {  // (cos, sin) form, no reduction
+                sh.t.tanh_phi[e] = static_cast<float>(cos(th));
+                sh.t.sin_phi[e] = static_cast<float>(sin(th));
+                sh.t.flip[e] = 1;
+                continue;
+            }
             // G(th) = f * G(phi) with |phi| <= pi/2
             const double pi = 3.141592653589793238462643383279502884;
             double phi = th;
@@ -122,10 +165,17 @@ __device__ void build_table(PlanShared& sh, int dir, int c, const float* __restr
                 // a pair whose stored signs differ is rotated by -phi
                 const float g = sm == sq ? 1.0f : -1.0f;
                 float* cp = cbase + static_cast<size_t>(p) * n;
-                cp[2 * tid + 0] = g * sh.t.tanh_phi[e];
-                cp[2 * tid + 1] = -g * sh.t.sin_phi[e];
-                sh.t.sign[m] = f * sm;
-                sh.t.sign[nn] = sm == sq ? f * sm : -f * sm;
+                if (k >= kLaneBits) {
+                    // stored (sm a, sq b) -> (sm a', sq b'): the sine is
+                    // multiplied by sm * sq, the signs stay
+                    cp[2 * tid + 0] = sh.t.tanh_phi[e];
+                    cp[2 * tid + 1] = g * sh.t.sin_phi[e];
+                } else {
+                    cp[2 * tid + 0] = g * sh.t.tanh_phi[e];
+                    cp[2 * tid + 1] = -g * sh.t.sin_phi[e];
+                    sh.t.sign[m] = f * sm;
+                    sh.t.sign[nn] = sm == sq ? f * sm : -f * sm;
+                }
             }
             __syncthreads();
         }
@@ -166,7 +216,7 @@ __device__ int block_exclusive_scan(int v, int* sh, int* total) {
 
 // Class counts of chunk k -> counts[k][c]; out-of-range classes set
 // chunk_err[k]. Without class indices every block is class 0.
-__device__ void count_chunk(PlanShared& sh, int64_t k, const int32_t* __restrict__ cls,
+__device__ void count_chunk(CountShared& sh, int64_t k, const int32_t* __restrict__ cls,
                             int64_t nblocks, int64_t chunk, int nclasses,
                             int32_t* __restrict__ counts, int32_t* __restrict__ chunk_err) {
     const int tid = threadIdx.x;
@@ -176,12 +226,24 @@ __device__ void count_chunk(PlanShared& sh, int64_t k, const int32_t* __restrict
     if (tid == 0) sh.flag = 0;
     __syncthreads();
     if (cls != nullptr) {
-        for (int i = tid; i < cnt; i += blockDim.x) {
-            const int c = cls[start + i];
-            if (c >= 0 && c < nclasses)
-                atomicAdd(&sh.c.hist[c], 1);
-            else
-                sh.flag = 1;
+        // kUnroll class loads in flight per thread before the LDS atomics
+        const int step = static_cast<int>(blockDim.x) * kUnroll;
+        for (int i0 = tid; i0 < cnt; i0 += step) {
+            int cv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = i0 + u * static_cast<int>(blockDim.x);
+                cv[u] = i < cnt ? cls[start + i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = i0 + u * static_cast<int>(blockDim.x);
+                if (i >= cnt) break;
+                if (cv[u] >= 0 && cv[u] < nclasses)
+                    atomicAdd(&sh.c.hist[cv[u]], 1);
+                else
+                    sh.flag = 1;
+            }
         }
     } else if (tid == 0) {
         sh.c.hist[0] = cnt;
@@ -200,7 +262,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(
     PlanHeader* __restrict__ hdr, int32_t* __restrict__ chunk_err,
     int32_t* __restrict__ counts, int32_t* __restrict__ modes, float* __restrict__ coef,
     float* __restrict__ signs) {
-    __shared__ PlanShared sh;
+    __shared__ CountShared sh;
     const int64_t wg = blockIdx.x;
     if (wg < 2 * nclasses) {
         build_table(sh, static_cast<int>(wg / nclasses), static_cast<int>(wg % nclasses), angles,
@@ -219,24 +281,45 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
     int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
     int32_t* __restrict__ tile_class, int32_t* __restrict__ perm) {
-    __shared__ PlanShared sh;
+    extern __shared__ __align__(16) int place_dyn[];
+    const PlaceLds sh = place_lds(place_dyn, nchunks, nclasses);
     const int tid = threadIdx.x;
     const int64_t k = blockIdx.x;
     const int64_t ncounts = nchunks * nclasses;
-    const bool cached = ncounts <= kCountsCache;
-    if (cached)
-        for (int64_t e = tid; e < ncounts; e += blockDim.x) sh.p.counts[e] = counts[e];
+    const bool cached = place_counts_cached(nchunks, nclasses);
+    if (cached) {
+        // 16-byte loads (counts starts 256-byte aligned), several in flight
+        const int64_t n4 = ncounts / 4;
+        const int4* c4 = reinterpret_cast<const int4*>(counts);
+        int4* s4 = reinterpret_cast<int4*>(sh.counts);  // sh.counts is at the LDS base
+#pragma unroll 4
+        for (int64_t e = tid; e < n4; e += blockDim.x) s4[e] = c4[e];
+        for (int64_t e = n4 * 4 + tid; e < ncounts; e += blockDim.x) sh.counts[e] = counts[e];
+    }
     __syncthreads();
-    for (int c = tid; c < nclasses; c += blockDim.x) {
-        int total = 0, pre = 0;
-        for (int64_t q = 0; q < nchunks; ++q) {
-            const int v = cached ? sh.p.counts[q * nclasses + c] : counts[q * nclasses + c];
-            total += v;
-            if (q < k) pre += v;
+    // Per class: blocks in the whole batch and in the chunks before this one.
+    // One wavefront per class at a time, its lanes striding over the chunks.
+    {
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        const int nwaves = blockDim.x >> 6;
+        for (int c = wave; c < nclasses; c += nwaves) {
+            int total = 0, pre = 0;
+            for (int64_t q = lane; q < nchunks; q += 64) {
+                const int v = cached ? sh.counts[q * nclasses + c] : counts[q * nclasses + c];
+                total += v;
+                if (q < k) pre += v;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                total += __shfl_xor(total, off, 64);
+                pre += __shfl_xor(pre, off, 64);
+            }
+            if (lane == 0) {
+                sh.total[c] = total;
+                sh.pre[c] = pre;
+                sh.pos[c] = 0;
+            }
         }
-        sh.p.total[c] = total;
-        sh.p.pre[c] = pre;
-        sh.p.pos[c] = 0;
     }
     __syncthreads();
     // First tile of each class: exclusive scan of the per-class tile counts,
@@ -245,24 +328,37 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     const int c0 = min(tid * per, nclasses);
     const int c1 = min(c0 + per, nclasses);
     int run = 0;
-    for (int c = c0; c < c1; ++c) run += class_tiles(sh.p.total[c]);
+    for (int c = c0; c < c1; ++c) run += class_tiles(sh.total[c]);
     int ntiles = 0;
-    int base = block_exclusive_scan(run, sh.p.scan, &ntiles);
+    int base = block_exclusive_scan(run, sh.scan, &ntiles);
     for (int c = c0; c < c1; ++c) {
-        sh.p.tile_base[c] = base;
-        base += class_tiles(sh.p.total[c]);
+        sh.tile_base[c] = base;
+        base += class_tiles(sh.total[c]);
     }
-    if (tid == 0) sh.p.tile_base[nclasses] = ntiles;
+    if (tid == 0) sh.tile_base[nclasses] = ntiles;
     __syncthreads();
     // Block ids of this chunk into their classes' tiles.
     const int64_t start = k * chunk;
     const int cnt = static_cast<int>(min<int64_t>(chunk, nblocks - start));
-    for (int i = tid; i < cnt; i += blockDim.x) {
-        const int c = cls != nullptr ? cls[start + i] : 0;
-        if (c >= 0 && c < nclasses) {
-            const int p = sh.p.pre[c] + atomicAdd(&sh.p.pos[c], 1);
-            perm[static_cast<int64_t>(sh.p.tile_base[c]) * kTile + p] =
-                static_cast<int32_t>(start + i);
+    const int step = static_cast<int>(blockDim.x) * kUnroll;
+    for (int i0 = tid; i0 < cnt; i0 += step) {
+        int cv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int i = i0 + u * static_cast<int>(blockDim.x);
+            cv[u] = (i < cnt && cls != nullptr) ? cls[start + i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int i = i0 + u * static_cast<int>(blockDim.x);
+            const int c = cv[u];
+            if (i < cnt && c >= 0 && c < nclasses) {
+                const int p = sh.pre[c] + atomicAdd(&sh.pos[c], 1);
+                const int64_t slot = static_cast<int64_t>(sh.tile_base[c]) * kTile + p;
+                // Counts and classes agree unless cls changed between the two
+                // plan launches; never write outside perm even then.
+                if (slot < max_tiles * kTile) perm[slot] = static_cast<int32_t>(start + i);
+            }
         }
     }
     // Class of every tile of this chunk's share of the tile list, and the
@@ -280,10 +376,10 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
         int lo = 0, hi = nclasses - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (sh.p.tile_base[mid] <= t) lo = mid; else hi = mid - 1;
+            if (sh.tile_base[mid] <= t) lo = mid; else hi = mid - 1;
         }
         tile_class[t] = lo;
-        const int used = sh.p.total[lo] - static_cast<int>(t - sh.p.tile_base[lo]) * kTile;
+        const int used = sh.total[lo] - static_cast<int>(t - sh.tile_base[lo]) * kTile;
         for (int s2 = max(used, 0); s2 < kTile; ++s2) perm[t * kTile + s2] = -1;
     }
 }
@@ -299,8 +395,15 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
                        p.coef, p.signs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const size_t lds = place_lds_bytes(l.nchunks, nclasses);
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(plan_place_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(plan_place_kernel, dim3(static_cast<unsigned>(l.nchunks)),
-                       dim3(kPlanThreads), 0, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
+                       dim3(kPlanThreads), lds, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
                        l.max_tiles, p.counts, p.tile_class, p.perm);
     return hipGetLastError();
 }

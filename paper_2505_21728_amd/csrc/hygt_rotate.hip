@@ -1,12 +1,16 @@
 // The HyGT rotation kernels: R rounds of log2(N) parallel-Givens passes over
 // a batch of blocks (Sec. IV, eq. (5)-(9)).
 //
-// Mapping (N <= 64). One wavefront owns a tile of 64 blocks of one class, one
-// lane per block, and keeps its block's N values in registers for all
-// passes: every butterfly of every pass is a register-to-register operation
-// with compile-time register indices, and the class's per-pass multipliers
-// are wave-uniform, so they arrive through scalar loads as SGPR operands of
-// the FMAs. Nothing is exchanged between lanes during the passes.
+// Mapping. One wavefront owns a tile of 64 blocks of one class, one lane per
+// block, and keeps its block's N values in registers for all passes: every
+// butterfly of every pass is a register-to-register operation with
+// compile-time register indices, and the class's per-pass multipliers are
+// wave-uniform, so they arrive through scalar loads as SGPR operands of the
+// FMAs. Nothing is exchanged between lanes during the passes. For N = 256 a
+// lane's registers cannot hold a block, so two wavefronts share the tile,
+// wavefront h holding values 128h .. 128h+127 of every block; the passes
+// along bit 7 pair the two halves, which swap values through LDS in parts of
+// 16 per lane.
 //
 // Memory. A tile moves between HBM and registers through LDS in both
 // directions, so that every global access covers whole blocks (or whole
@@ -43,11 +47,14 @@ namespace {
 constexpr int kWaves = 4;
 // Accelerator complex dies (XCDs) that workgroups are dispatched over.
 constexpr int kXcds = 8;
-// Register budget of the rotation kernels: resident wavefronts per SIMD.
+// Register budget of the rotation kernels: resident wavefronts per SIMD
+// (N <= 64; a lane holding 128 values needs about 160 registers, three
+// wavefronts per SIMD).
 #ifndef HYGT_WAVES_PER_SIMD
 #define HYGT_WAVES_PER_SIMD 5
 #endif
 constexpr int kWavesPerSimd = HYGT_WAVES_PER_SIMD;
+constexpr int kWavesPerSimdWide = 3;
 
 template <int I, int End>
 struct StaticFor {
@@ -126,6 +133,76 @@ __device__ __forceinline__ void run_passes(float (&v)[T][1 << D], const float* _
     }
 }
 
+// N = 256: a pass along bit 7 pairs value j of wavefront 0 (element j) with
+// value j of wavefront 1 (element 128 + j). The wavefronts swap their values
+// through LDS, 16 per lane at a time, and each computes its own outputs:
+// y_m = c x_m + s x_n on wavefront 0, y_n = c x_n - s x_m on wavefront 1,
+// with (c, s) = cp[2j], cp[2j + 1]. `xo` is this wavefront's exchange area
+// and `xp` the other's, each two buffers of [4][64] float4; part g uses
+// buffer g % 2, so the barrier of part g + 1 also guarantees that both
+// wavefronts have read part g before either overwrites its buffer.
+__device__ __forceinline__ void cross_pass(float (&v)[128], const float* __restrict__ cp,
+                                           unsigned hbit, float4* xo, const float4* xp,
+                                           int lane) {
+    StaticFor<0, 8>::run([&](auto gg) {
+        constexpr int g = decltype(gg)::value;
+        constexpr int buf = g & 1;
+        StaticFor<0, 4>::run([&](auto qq) {
+            constexpr int q = decltype(qq)::value;
+            constexpr int e = 16 * g + 4 * q;
+            xo[(buf * 4 + q) * 64 + lane] = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+        });
+        __syncthreads();
+        float w[16];
+        StaticFor<0, 4>::run([&](auto qq) {
+            constexpr int q = decltype(qq)::value;
+            const float4 f = xp[(buf * 4 + q) * 64 + lane];
+            w[4 * q + 0] = f.x;
+            w[4 * q + 1] = f.y;
+            w[4 * q + 2] = f.z;
+            w[4 * q + 3] = f.w;
+        });
+        StaticFor<0, 16>::run([&](auto tt) {
+            constexpr int t = decltype(tt)::value;
+            constexpr int j = 16 * g + t;
+            const float c = cp[2 * j];
+            const float sn = cp[2 * j + 1];
+            // -s on wavefront 1: a sign-bit flip of a wave-uniform value
+            const float sg = __uint_as_float(__float_as_uint(sn) ^ hbit);
+            v[j] = fmaf(sg, w[t], c * v[j]);
+        });
+    });
+}
+
+// N = 256, wavefront h of a tile: R rounds of 8 passes in application order.
+// Passes along bits 0..6 act on the lane's 128 values with the multipliers
+// of pairs 64h .. 64h + 63 of the pass; passes along bit 7 go through
+// cross_pass. Then the final signs of elements 128h .. 128h + 127.
+template <int DIR>
+__device__ __forceinline__ void run_passes_split(float (&v)[1][128], const float* __restrict__ tbl,
+                                                 const float* __restrict__ sign, int has_neg,
+                                                 int rounds, int h, float4* xo, const float4* xp,
+                                                 int lane) {
+    constexpr int D = 8;
+    constexpr int N = 256;
+    for (int r = 0; r < rounds; ++r) {
+        StaticFor<0, D>::run([&](auto kk) {
+            constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
+            const float* cp = tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N;
+            if constexpr (K >= kLaneBits)
+                cross_pass(v[0], cp, static_cast<unsigned>(h) << 31, xo, xp, lane);
+            else
+                pass_lift<kLaneBits, K, 1>(v, cp + h * (N / 2));
+        });
+    }
+    if (has_neg) {
+        StaticFor<0, N / 2>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            v[0][i] *= sign[h * (N / 2) + i];
+        });
+    }
+}
+
 __device__ __forceinline__ int valid_block(int b, int64_t nblocks) {
     return (b >= 0 && b < nblocks) ? b : -1;  // never touch memory outside x / y
 }
@@ -140,10 +217,16 @@ constexpr int kChunksPerPart = HYGT_CHUNKS_PER_PART;
 template <int D>
 struct TileGeo {
     static constexpr int N = 1 << D;
-    static constexpr int CH = N / 4;                 // 16-byte chunks per block
-    static constexpr int CHP = CH < kChunksPerPart ? CH : kChunksPerPart;  // per part
+    static constexpr bool SPLIT = D > kLaneBits;     // two wavefronts per tile
+    static constexpr int V = SPLIT ? N / 2 : N;      // values per lane
+    static constexpr int LD = SPLIT ? kLaneBits : D; // log2(V)
+    static constexpr int CH = V / 4;                 // 16-byte chunks per lane's row
+    static constexpr int CHP = CH < 1 ? 1 : CH < kChunksPerPart ? CH : kChunksPerPart;  // per part
     static constexpr int PARTS = CH / CHP;
     static constexpr int BPI = 64 / CHP;             // blocks per memory instruction
+    static constexpr int WAVES = SPLIT ? 2 : kWaves;  // wavefronts per workgroup
+    static constexpr int TILES = SPLIT ? 1 : kWaves;  // tiles per workgroup
+    static constexpr int OCC = D < 7 ? kWavesPerSimd : kWavesPerSimdWide;
 };
 
 // Block id handled by memory instruction i of every part: block
@@ -158,8 +241,9 @@ __device__ __forceinline__ void instr_blocks(int* bb, int blk, int lane) {
 }
 
 // Instruction i of part `part` fetches, for block b = i*BPI + lane/CHP, the chunk
-// part*CHP + ((lane%CHP) ^ swz(b)) into LDS slot i*64 + lane, which is
-// b*CHP + (chunk-in-part ^ swz(b)).
+// part*CHP + ((lane%CHP) ^ swz(b)) of its row into LDS slot i*64 + lane, which
+// is b*CHP + (chunk-in-part ^ swz(b)). Rows are N floats apart; a lane's row
+// is the whole block, or for N = 256 the half that x and y point into.
 template <int D>
 __device__ __forceinline__ void gather_part(const float* __restrict__ x, float4* L,
                                             const int* bb, int lane, int part) {
@@ -246,15 +330,18 @@ __device__ __forceinline__ int64_t xcd_tile_group() {
     return (w % kXcds) * per_xcd + w / kXcds;
 }
 
-// N >= 4: LDS-staged tiles, one lane per block, one tile per wavefront.
+// N >= 4: LDS-staged tiles, one lane per block; one tile per wavefront, or
+// for N = 256 one tile per pair of wavefronts (a workgroup), wavefront h
+// holding half h of every block.
 //
-// x and y may be the same array (in place): every block is read by the
+// x and y may be the same array (in place): every value is read by the
 // wavefront that owns it and written back only after that read has
 // completed, and no other wavefront touches it, so the restrict qualifiers
 // (which let the per-tile class loads stay scalar) hold for every pair of
 // accesses that the compiler could reorder.
 template <int D, int DIR, int RT>
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd)))
+__global__ __launch_bounds__(64 * TileGeo<D>::WAVES)
+__attribute__((amdgpu_waves_per_eu(TileGeo<D>::OCC)))
 void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t nblocks,
                    int rounds, int nclasses, int64_t max_tiles,
                    const int32_t* __restrict__ tile_class, const int32_t* __restrict__ perm,
@@ -263,19 +350,24 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
     using G = TileGeo<D>;
     constexpr int N = G::N;
     constexpr int CHP = G::CHP;
-    constexpr int T = kTilesPerWave;
-    __shared__ float4 lds[kWaves][kTile * CHP];
+    constexpr int T = G::SPLIT ? 1 : kTilesPerWave;
+    // Staging of a part; for N = 256 also the exchange area (2 x 4 x 64 float4).
+    __shared__ float4 lds[G::WAVES][kTile * CHP];
+    static_assert(!G::SPLIT || kTile * CHP >= 2 * 4 * 64, "exchange area too small");
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = G::SPLIT ? wv : 0;  // half of every block held by this wavefront
     // This wavefront's T consecutive tiles; the plan gives them one class.
-    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * T;
-    if (t0 >= max_tiles) return;
+    const int64_t t0 = G::SPLIT ? xcd_tile_group() : (xcd_tile_group() * kWaves + wv) * T;
+    if (t0 >= max_tiles) return;  // both wavefronts of a split tile leave together
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;  // past the last tile
+    const float* xh = x + h * G::V;
+    float* yh = y + h * G::V;
     float4* L = lds[wv];
     int blk[T];
-    float v[T][N];
+    float v[T][G::V];
     {
         const int sw = swz<CHP>(lane);
         StaticFor<0, T>::run([&](auto uu) {
@@ -283,15 +375,24 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
             blk[u] = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
             int bb[CHP];
             instr_blocks<D>(bb, blk[u], lane);
-            load_part<D, 0>(x, L, bb, v[u], lane, sw);
-            if constexpr (G::PARTS > 1) load_part<D, 1>(x, L, bb, v[u], lane, sw);
+            StaticFor<0, G::PARTS>::run([&](auto pp) {
+                load_part<D, decltype(pp)::value>(xh, L, bb, v[u], lane, sw);
+            });
         });
     }
 
     const size_t passes = static_cast<size_t>(rounds) * D;
     const size_t table = static_cast<size_t>(DIR) * nclasses + c;
-    run_passes<D, DIR, RT, T>(v, coef + table * passes * N, signs + table * N, modes[table],
-                              rounds);
+    if constexpr (G::SPLIT) {
+        run_passes_split<DIR>(v, coef + table * passes * N, signs + table * N, modes[table],
+                              rounds, h, lds[h], lds[1 - h], lane);
+        // The other wavefront's last reads of this wavefront's exchange area
+        // come before the stores below reuse it for staging.
+        __syncthreads();
+    } else {
+        run_passes<D, DIR, RT, T>(v, coef + table * passes * N, signs + table * N,
+                                  modes[table], rounds);
+    }
 
     // Addresses for the way out are derived again from the block ids and the
     // lane index, made opaque here so that the compiler does not keep the
@@ -305,8 +406,9 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
         asm volatile("" : "+v"(b));
         int bb[CHP];
         instr_blocks<D>(bb, b, lane2);
-        store_part<D, 0>(y, L, bb, v[u], lane2, sw2);
-        if constexpr (G::PARTS > 1) store_part<D, 1>(y, L, bb, v[u], lane2, sw2);
+        StaticFor<0, G::PARTS>::run([&](auto pp) {
+            store_part<D, decltype(pp)::value>(yh, L, bb, v[u], lane2, sw2);
+        });
     });
 }
 
@@ -339,10 +441,11 @@ __global__ __launch_bounds__(64 * kWaves) void rotate_kernel_n2(
 template <int D, int DIR, int RT>
 hipError_t launch_one(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
                       const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
-    const int64_t per_group = static_cast<int64_t>(kWaves) * kTilesPerWave;
+    using G = TileGeo<D>;
+    const int64_t per_group = G::SPLIT ? 1 : static_cast<int64_t>(kWaves) * kTilesPerWave;
     const int64_t groups = (l.max_tiles + per_group - 1) / per_group;
     const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
-    const dim3 block(64 * kWaves);
+    const dim3 block(D == 1 ? 64 * kWaves : 64 * G::WAVES);
     if constexpr (D == 1)
         hipLaunchKernelGGL((rotate_kernel_n2<DIR>), grid, block, 0, stream, x, y, nblocks,
                            rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes, p.coef,
@@ -358,8 +461,10 @@ hipError_t launch_one(const float* x, float* y, int64_t nblocks, int rounds, int
 template <int D, int DIR>
 hipError_t launch_rounds(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
                          const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
-    if constexpr (D == 1) {
-        return launch_one<1, DIR, 0>(x, y, nblocks, rounds, nclasses, l, p, stream);
+    if constexpr (D == 1 || D >= 7) {
+        // N = 2, and N >= 128 (whose unrolled rounds would not fit the
+        // instruction cache), loop over the rounds.
+        return launch_one<D, DIR, 0>(x, y, nblocks, rounds, nclasses, l, p, stream);
     } else {
         switch (rounds) {
             case 1: return launch_one<D, DIR, 1>(x, y, nblocks, rounds, nclasses, l, p, stream);
@@ -382,6 +487,8 @@ hipError_t launch_dir(const float* x, float* y, int64_t nblocks, int log2n, int 
         case 4: return launch_rounds<4, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
         case 5: return launch_rounds<5, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
         case 6: return launch_rounds<6, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        case 7: return launch_rounds<7, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        case 8: return launch_rounds<8, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
         default: return hipErrorInvalidValue;
     }
 }

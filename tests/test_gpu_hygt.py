@@ -93,11 +93,11 @@ def test_config2_small_parity():
     _parity(x, cls, ang, dev, "cfg2-small")
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("rounds", [1, 2, 3, 5, 7])
 def test_sizes_sweep(d, rounds):
-    """Every N <= 64, unrolled (R <= 5) and looping (R = 7) kernels, 3 classes,
-    a ragged batch (not a multiple of 64)."""
+    """Every N from 2 to 256, unrolled (R <= 5, N <= 64) and looping kernels,
+    3 classes, a ragged batch (not a multiple of 64)."""
     dev = _dev()
     rng = np.random.default_rng(100 + 10 * d + rounds)
     nb = 300
@@ -117,9 +117,10 @@ def test_ragged_batches(nb):
     _parity(x, cls, ang, dev, f"ragged nb={nb}")
 
 
-def test_direct_schedule_classes():
-    """Angles near +-pi/2 drive the scale factors out of range: those classes
-    take the direct schedule; parity must hold for both schedules."""
+def test_sign_flip_classes():
+    """Angles at and beyond +-pi/2: the kernels rotate by the reduced angle
+    and carry sign flips through the passes; classes made only of such angles
+    must still match the oracle."""
     dev = _dev()
     rng = np.random.default_rng(7)
     ang = rng.uniform(-math.pi, math.pi, (4, 4, 6, 32)).astype(np.float32)
@@ -132,12 +133,21 @@ def test_direct_schedule_classes():
     ang16 = np.full((1, 2, d, 8), np.float32(math.pi / 2), dtype=np.float32)
     x16 = synth.gaussian_blocks(500, 16)
     _parity(x16, np.zeros(500, np.int32), ang16, dev, "all pi/2 N=16")
+    # N = 256: the passes along bit 7 run between two wavefronts and take
+    # the stored signs of both halves into account
+    ang256 = rng.uniform(-math.pi, math.pi, (4, 3, 8, 128)).astype(np.float32)
+    ang256[1] = np.float32(math.pi / 2)
+    ang256[2, :, :7] = np.float32(-math.pi)
+    ang256[3, :, 7] = np.float32(3.0)
+    x256 = synth.ar1_blocks(700, 16, seed=9)
+    cls256 = rng.integers(0, 4, 700).astype(np.int32)
+    _parity(x256, cls256, ang256, dev, "sign-flip classes N=256")
 
 
 def test_zero_angles_identity_and_zero_blocks():
     dev = _dev()
     hygt = _hygt()
-    for d in (1, 4, 6):
+    for d in (1, 4, 6, 7, 8):
         ang = np.zeros((2, 3, d, 1 << (d - 1)), dtype=np.float32)
         x = synth.gaussian_blocks(200, 1 << d, seed=d)
         x[::7] = 0
@@ -175,6 +185,31 @@ def test_batch_invariance_and_in_place():
     plan.inverse(xi, out=xi)
     z_out = plan.inverse(_to(y_full, dev)).cpu().numpy()
     assert np.array_equal(xi.cpu().numpy(), z_out)
+
+
+@pytest.mark.parametrize("d", [7, 8])
+def test_wide_blocks_parity_and_invariance(d):
+    """N = 128 and N = 256 (16x16 AR(1) blocks for d = 8): 35 classes, several
+    tiles per class and a ragged tail; bit-identical results for a shuffled
+    sub-batch and in place."""
+    dev = _dev()
+    hygt = _hygt()
+    nb = 4097
+    ang = synth.angles(35, 4, d)
+    if d == 8:
+        x = synth.ar1_blocks(nb, 16, seed=14)
+    else:
+        x = synth.gaussian_blocks(nb, 1 << d, seed=14)
+    cls = synth.classes(nb, 35, seed=15)
+    _parity(x, cls, ang, dev, f"wide d={d}")
+    at, xt = _to(ang, dev), _to(x, dev)
+    y_full = hygt.Plan(at, _to(cls, dev)).forward(xt).cpu().numpy()
+    sub = np.random.default_rng(16).permutation(nb)[:300]
+    y_sub = hygt.Plan(at, _to(cls[sub], dev)).forward(_to(x[sub], dev)).cpu().numpy()
+    assert np.array_equal(y_sub, y_full[sub])
+    xi = xt.clone()
+    hygt.Plan(at, _to(cls, dev)).forward(xi, out=xi)
+    assert np.array_equal(xi.cpu().numpy(), y_full)
 
 
 def test_out_of_range_class():
