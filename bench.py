@@ -26,7 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = ("blocks/sec and achieved HBM GB/s (% peak), HyGT fwd+inv N=64; "
+          "p50/p99 serve latency")
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak, GB/s
+# Counter-based HBM traffic of the forward rotation kernel, measured with
+# rocprofv3 (FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size);
+# used only while the kernel sources still hash to the recorded value.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rotate_kernel_n64_2p20_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_21728_amd", "csrc", f)
+                  for f in ("hygt_rotate.hip", "hygt_internal.h")]
 NBLOCKS = 1 << 20
 LOG2N = 6
 N = 1 << LOG2N
@@ -58,6 +66,32 @@ def _copy_calibration(torch, dev):
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
                       "launches": 5}))
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _measured_traffic():
+    """Bytes per forward launch from the committed counter summary, or None
+    when it is missing or was taken on other kernel sources."""
+    import re
+
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    sha = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    val = re.search(r"^traffic_bytes_per_launch_forward:\s*(\d+)", text, re.M)
+    if not sha or not val or sha.group(1) != kernel_source_sha256():
+        return None
+    return int(val.group(1))
 
 
 def _cpu_baseline(x, cls, ang, sample):
@@ -146,7 +180,7 @@ def main():
         cpu = _cpu_baseline(x, cls, ang, min(args.cpu_sample, NBLOCKS))
 
     out = {
-        "metric": "blocks/sec and achieved HBM GB/s (% peak), HyGT fwd+inv N=64",
+        "metric": METRIC,
         "value": value,
         "unit": "blocks/s",
         "n_gpus": 1,
@@ -166,7 +200,8 @@ def main():
         "fwd_ms": fwd_ms,
         "inv_ms": inv_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": _measured_traffic(),
                      "kernel": "rotate_kernel<6,0,4> (forward)",
                      "bytes_per_launch": launch_bytes,
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
