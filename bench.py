@@ -94,6 +94,47 @@ def _measured_traffic():
     return int(val.group(1))
 
 
+def _klt_comparison(torch, hygt, at, ct, xt, steps):
+    """The dense per-class transform (BF16 MFMA grouped GEMM) on the same
+    blocks and classes, with M_c = T_c (forward) and T_c^T (inverse) of the
+    same angles. The matrices are materialised on the GPU by the HyGT path:
+    the inverse of the unit vectors gives the rows of T_c, the forward its
+    columns."""
+    dev = xt.device
+    C = NCLASSES
+    eye = torch.eye(N, dtype=torch.float32, device=dev).repeat(C, 1).contiguous()
+    eye_cls = torch.arange(C, dtype=torch.int32, device=dev).repeat_interleave(N).contiguous()
+    p_eye = hygt.Plan(at, eye_cls)
+    mats = p_eye.inverse(eye).view(C, N, N).to(torch.bfloat16).contiguous()
+    mats_t = p_eye.forward(eye).view(C, N, N).to(torch.bfloat16).contiguous()
+    plan = hygt.Plan(at, ct)
+    y = torch.empty_like(xt)
+    z = torch.empty_like(xt)
+    for _ in range(3):
+        plan.dense(xt, mats, out=y)
+        plan.dense(y, mats_t, out=z)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        ev[4 * i].record(stream)
+        plan.dense(xt, mats, out=y)
+        ev[4 * i + 1].record(stream)
+        ev[4 * i + 2].record(stream)
+        plan.dense(y, mats_t, out=z)
+        ev[4 * i + 3].record(stream)
+    torch.cuda.synchronize()
+    fwd = sum(ev[4 * i].elapsed_time(ev[4 * i + 1]) for i in range(steps)) / steps
+    inv = sum(ev[4 * i + 2].elapsed_time(ev[4 * i + 3]) for i in range(steps)) / steps
+    launch_bytes = NBLOCKS * BYTES_PER_BLOCK
+    return {"kernel": "dense_kernel (BF16 MFMA 16x16x32, FP32 accumulate)",
+            "fwd_ms": fwd, "inv_ms": inv,
+            "fwd_gbps": launch_bytes / (fwd / 1e3) / 1e9,
+            "flops_per_launch": NBLOCKS * 2 * N * N,
+            "matrix_bytes_bf16": C * N * N * 2,
+            "hygt_angle_bytes_f32": C * ROUNDS * LOG2N * (N // 2) * 4}
+
+
 def _cpu_baseline(x, cls, ang, sample):
     from oracle import hygt_oracle as orc
 
@@ -175,6 +216,8 @@ def main():
     achieved = launch_bytes / (fwd_ms / 1e3) / 1e9
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
+    klt = _klt_comparison(torch, hygt, at, ct, xt, args.steps)
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = _cpu_baseline(x, cls, ang, min(args.cpu_sample, NBLOCKS))
@@ -205,6 +248,7 @@ def main():
                      "kernel": "rotate_kernel<6,0,4> (forward)",
                      "bytes_per_launch": launch_bytes,
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
+        "klt_dense": klt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

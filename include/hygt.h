@@ -134,6 +134,28 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks,
                  int log2n, int rounds, const float* angles, int nclasses,
                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Block length (log2) supported by hygt_dense_apply(). */
+#define HYGT_DENSE_LOG2N 6
+
+/* The matrix-based transform that HyGT replaces, for comparison: the dense
+ * per-class transform y[b] = M_{cls[b]} x[b] of eq. (3) (a KLT when M_c holds
+ * the eigenvectors of the class's covariance, Sec. II), whose cost Table I
+ * gives as N^2 operations and N^2 stored values per class. Runs on the
+ * matrix cores as a grouped GEMM over the class-sorted tiles of the plan in
+ * the workspace (only its class grouping is used, so the sizes must be
+ * those of that hygt_plan() call).
+ *   mats   BF16 bit patterns [nclasses][N][N], row-major (mats[c][i][j] is
+ *          M_c[i][j]), 16-byte aligned; read only.
+ *   x, y   as for hygt_apply(); N must be 64 (log2n == HYGT_DENSE_LOG2N).
+ * Each x value is rounded to BF16 (to nearest, ties to even) before the
+ * products, which are summed in FP32 (exact for integer residuals of at most
+ * 8 significant bits, such as the [-255, 255] range of 8-bit video). Blocks
+ * whose class was out of range are left unwritten. For T_c^T (the inverse of
+ * an orthogonal T_c) pass the transposed matrices. */
+int hygt_dense_apply(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                     int nclasses, const uint16_t* mats,
+                     const void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Waits for `stream`, then reports whether the last non-empty plan on this
  * workspace met a class index outside [0, nclasses) (HYGT_ECLASS), a HIP
  * error (HYGT_EHIP), or neither (HYGT_OK). Reads at most workspace_bytes

@@ -16,8 +16,8 @@ from __future__ import annotations
 import math
 
 from . import _abi
-from ._abi import (HYGT_FORWARD, HYGT_INVERSE, HYGT_MAX_BLOCKS, HYGT_MAX_CLASSES,
-                   HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS, HygtError)
+from ._abi import (HYGT_DENSE_LOG2N, HYGT_FORWARD, HYGT_INVERSE, HYGT_MAX_BLOCKS,
+                   HYGT_MAX_CLASSES, HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS, HygtError)
 
 __all__ = ["Plan", "forward", "inverse", "workspace_bytes", "HygtError",
            "HYGT_FORWARD", "HYGT_INVERSE"]
@@ -129,6 +129,30 @@ class Plan:
     def inverse(self, x, out=None):
         """y[b] = T_{cls[b]}^T x[b] (eq. (6) and (9))."""
         return self.apply(x, HYGT_INVERSE, out)
+
+    def dense(self, x, mats, out=None):
+        """y[b] = M_{cls[b]} x[b] with BF16 matrices mats [C, N, N] on the
+        matrix cores (the dense transform of eq. (3)); N = 64 only."""
+        torch = _torch()
+        self._check_x(x)
+        _require(self.log2n == HYGT_DENSE_LOG2N, "dense transform needs N = 64")
+        _require(isinstance(mats, torch.Tensor), "mats must be a torch.Tensor", TypeError)
+        _require(mats.dtype == torch.bfloat16, "mats must be bfloat16", TypeError)
+        _require(mats.device == self.device and mats.is_contiguous(),
+                 "mats must be contiguous on the plan's device")
+        _require(tuple(mats.shape) == (self.nclasses, self.n, self.n),
+                 f"mats must be [{self.nclasses}, {self.n}, {self.n}]")
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            self._check_x(out)
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_dense_apply(x.data_ptr(), out.data_ptr(), self.nblocks, self.log2n,
+                                       self.rounds, self.nclasses, mats.data_ptr(),
+                                       self.workspace.data_ptr(), self.ws_bytes,
+                                       _stream_handle(self._stream))
+        _abi._check(st, "hygt_dense_apply")
+        return out
 
     def check(self):
         """Synchronises and raises HygtError if a class index was out of range."""

@@ -27,6 +27,7 @@ HYGT_MAX_LOG2N = 8
 HYGT_MAX_ROUNDS = 64
 HYGT_MAX_CLASSES = 4096
 HYGT_MAX_BLOCKS = 2147483647
+HYGT_DENSE_LOG2N = 6
 
 # Every exported symbol with its (restype, argtypes).
 _c = ctypes
@@ -42,6 +43,9 @@ _SIGNATURES = {
     "hygt_inverse": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int,
                                 _c.c_int, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_size_t,
                                 _c.c_void_p]),
+    "hygt_dense_apply": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
+                                    _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                    _c.c_void_p]),
     "hygt_check_error": (_c.c_int, [_c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_strerror": (_c.c_char_p, [_c.c_int]),
 }
@@ -118,6 +122,12 @@ def hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, ncla
                  ws_bytes, stream) -> int:
     return load().hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr,
                                nclasses, ws_ptr, ws_bytes, stream)
+
+
+def hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr, ws_ptr, ws_bytes,
+                     stream) -> int:
+    return load().hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr,
+                                   ws_ptr, ws_bytes, stream)
 
 
 def hygt_check_error(ws_ptr, ws_bytes, stream) -> int:

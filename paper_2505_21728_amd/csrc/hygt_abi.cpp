@@ -66,6 +66,22 @@ int apply_impl(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
     return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 
+int dense_impl(const float* x, float* y, int64_t nblocks, int log2n, int rounds, int nclasses,
+               const uint16_t* mats, const void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!sizes_ok(nblocks, log2n, rounds, nclasses)) return HYGT_EINVAL;
+    if (log2n != HYGT_DENSE_LOG2N) return HYGT_EINVAL;
+    const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
+    if (int s = check_workspace(ws, ws_bytes, l)) return s;
+    if (nblocks == 0) return HYGT_OK;
+    if (x == nullptr || y == nullptr || mats == nullptr) return HYGT_EINVAL;
+    if (!aligned(x, 16) || !aligned(y, 16) || !aligned(mats, 16)) return HYGT_EINVAL;
+    if (!overlap_ok(x, y, nblocks, log2n)) return HYGT_EINVAL;
+    const hipError_t e =
+        hygt::launch_dense(x, y, nblocks, reinterpret_cast<const unsigned short*>(mats), l,
+                           hygt::ws_ptrs(const_cast<void*>(ws), l), stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
 int plan_and_apply(const float* x, float* y, const int32_t* cls, int64_t nblocks, int log2n,
                    int rounds, const float* angles, int nclasses, int direction, void* ws,
                    size_t ws_bytes, hipStream_t stream) {
@@ -117,6 +133,13 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks, 
                  size_t workspace_bytes, hipStream_t stream) {
     return plan_and_apply(x, y, cls, nblocks, log2n, rounds, angles, nclasses, HYGT_INVERSE,
                           workspace, workspace_bytes, stream);
+}
+
+int hygt_dense_apply(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                     int nclasses, const uint16_t* mats, const void* workspace,
+                     size_t workspace_bytes, hipStream_t stream) {
+    return dense_impl(x, y, nblocks, log2n, rounds, nclasses, mats, workspace, workspace_bytes,
+                      stream);
 }
 
 int hygt_check_error(const void* workspace, size_t workspace_bytes, hipStream_t stream) {

@@ -114,7 +114,7 @@ inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
     return p;
 }
 
-// Kernel launchers (hygt_plan.hip, hygt_rotate.hip). Each returns the
+// Kernel launchers (hygt_plan.hip, hygt_rotate.hip, hygt_dense.hip). Each returns the
 // hipError_t of its launches.
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
                        const float* angles, int nclasses, const WsLayout& l,
@@ -123,5 +123,9 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
 hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                          int nclasses, int direction, const WsLayout& l, const WsPtrs& p,
                          hipStream_t stream);
+
+// Dense per-class transform (hygt_dense.hip), N = 64.
+hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,
+                        const WsLayout& l, const WsPtrs& p, hipStream_t stream);
 
 }  // namespace hygt

@@ -116,3 +116,17 @@ def test_forward_inverse_reject_before_planning():
         assert fn(FAKE, FAKE + 256, FAKE, 100, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_EINVAL
         assert fn(0, FAKE, FAKE, 100, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_EINVAL
         assert fn(FAKE, FAKE * 8, FAKE, 0, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_OK
+
+
+def test_dense_rejects():
+    need = _abi.hygt_workspace_bytes(100, 6, 2, 3)
+    d = _abi.hygt_dense_apply
+    x, y, m = FAKE, FAKE * 4, FAKE * 8
+    need4 = _abi.hygt_workspace_bytes(100, 4, 2, 3)
+    assert d(x, y, 100, 4, 2, 3, m, FAKE, need4, 0) == _abi.HYGT_EINVAL       # N != 64
+    assert d(x, y, 100, 6, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL        # mats NULL
+    assert d(x, y, 100, 6, 2, 3, m + 2, FAKE, need, 0) == _abi.HYGT_EINVAL    # mats misaligned
+    assert d(x + 8, y, 100, 6, 2, 3, m, FAKE, need, 0) == _abi.HYGT_EINVAL    # x misaligned
+    assert d(x, x + 256, 100, 6, 2, 3, m, FAKE, need, 0) == _abi.HYGT_EINVAL  # overlap
+    assert d(x, y, 100, 6, 2, 3, m, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert d(0, 0, 0, 6, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_OK              # empty no-op
