@@ -102,9 +102,9 @@ size_t hygt_workspace_bytes(int64_t nblocks, int log2n, int rounds, int nclasses
 /* Builds, in the workspace, everything that depends on the classes and the
  * angles but not on the data (two kernel launches):
  *   - the multiplier tables of both directions: every angle converted in
- *     FP64 into per-pass FP32 multipliers (Sec. IV keeps the parameters
- *     compact and converts them to higher-precision multipliers when they
- *     are used): the two multipliers of a three-step lifting form of each
+ *     FP64 into per-pass FP32 multipliers (Sec. IV and Fig. 6 store
+ *     compact parameters and expand them into wider multipliers at use):
+ *     the two multipliers of a three-step lifting form of each
  *     rotation, or for N = 256 and the passes along bit 7, its cosine and
  *     sine;
  *   - the blocks sorted by class over the whole batch into tiles of 64

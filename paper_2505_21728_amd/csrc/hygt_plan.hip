@@ -1,9 +1,9 @@
 // Plan kernels: per-class multiplier tables and the grouping of blocks into
 // class-uniform tiles.
 //
-// Multiplier tables. Sec. IV of the paper keeps the transform parameters
-// compact and converts them to higher-precision multipliers only when they
-// are needed. Here every FP32 angle is converted, in FP64, into the two
+// Multiplier tables. Sec. IV and Fig. 6 store the transform parameters in a
+// compact form and expand them into wider multipliers at use. Here every
+// FP32 angle is converted, in FP64, into the two
 // multipliers of a lifting (three-shear) form of its Givens rotation, rounded
 // once to FP32:
 //
