@@ -7,6 +7,12 @@ each, uniform in [-pi, pi)). One step = the whole hot path on that batch:
 plan (multiplier tables + class grouping), forward transform, inverse
 transform. Inputs are resident in HBM before timing starts.
 
+The timed steps cycle over RING distinct input batches (the batch and its
+classes rotated by a different number of blocks each), 1 GiB of inputs in
+all: four times the 256 MB last-level cache of the MI355X, so every step
+reads its inputs from HBM rather than from a cache warmed by the step
+before.
+
 Prints one JSON line: blocks/s for forward + inverse, the roofline of the
 dominant kernel (the forward rotation, timed with HIP events on the stream it
 runs on), and the FP64 oracle timed on a bounded sample on the host.
@@ -36,6 +42,7 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rotate_kernel_n64_2p20_hbm_tra
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_21728_amd", "csrc", f)
                   for f in ("hygt_rotate.hip", "hygt_internal.h")]
 NBLOCKS = 1 << 20
+RING = 4                      # distinct input batches cycled by the timed steps
 LOG2N = 6
 N = 1 << LOG2N
 ROUNDS = 4
@@ -94,31 +101,32 @@ def _measured_traffic():
     return int(val.group(1))
 
 
-def _klt_comparison(torch, hygt, at, ct, xt, steps):
+def _klt_comparison(torch, hygt, at, cs, xs, steps):
     """The dense per-class transform (BF16 MFMA grouped GEMM) on the same
     blocks and classes, with M_c = T_c (forward) and T_c^T (inverse) of the
     same angles. The matrices are materialised on the GPU by the HyGT path:
     the inverse of the unit vectors gives the rows of T_c, the forward its
     columns."""
-    dev = xt.device
+    dev = xs[0].device
     C = NCLASSES
     eye = torch.eye(N, dtype=torch.float32, device=dev).repeat(C, 1).contiguous()
     eye_cls = torch.arange(C, dtype=torch.int32, device=dev).repeat_interleave(N).contiguous()
     p_eye = hygt.Plan(at, eye_cls)
     mats = p_eye.inverse(eye).view(C, N, N).to(torch.bfloat16).contiguous()
     mats_t = p_eye.forward(eye).view(C, N, N).to(torch.bfloat16).contiguous()
-    plan = hygt.Plan(at, ct)
-    y = torch.empty_like(xt)
-    z = torch.empty_like(xt)
-    for _ in range(3):
-        plan.dense(xt, mats, out=y)
-        plan.dense(y, mats_t, out=z)
+    plans = [hygt.Plan(at, c) for c in cs]
+    y = torch.empty_like(xs[0])
+    z = torch.empty_like(xs[0])
+    for k in range(3):
+        plans[k % RING].dense(xs[k % RING], mats, out=y)
+        plans[k % RING].dense(y, mats_t, out=z)
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
     torch.cuda.synchronize()
     for i in range(steps):
+        plan = plans[i % RING]
         ev[4 * i].record(stream)
-        plan.dense(xt, mats, out=y)
+        plan.dense(xs[i % RING], mats, out=y)
         ev[4 * i + 1].record(stream)
         ev[4 * i + 2].record(stream)
         plan.dense(y, mats_t, out=z)
@@ -170,8 +178,12 @@ def main():
     ang = synth.angles(NCLASSES, ROUNDS, LOG2N)
     x = synth.ar1_blocks(NBLOCKS, 8)
     cls = synth.classes(NBLOCKS, NCLASSES)
-    xt = torch.from_numpy(x).to(dev)
-    ct = torch.from_numpy(cls).to(dev)
+    x0 = torch.from_numpy(x).to(dev)
+    c0 = torch.from_numpy(cls).to(dev)
+    shift = NBLOCKS // RING + 12345
+    xs = [torch.roll(x0, k * shift, 0).contiguous() for k in range(RING)]
+    cs = [torch.roll(c0, k * shift, 0).contiguous() for k in range(RING)]
+    xt, ct = xs[0], cs[0]
     at = torch.from_numpy(ang).to(dev)
     yt = torch.empty_like(xt)
     zt = torch.empty_like(xt)
@@ -182,11 +194,11 @@ def main():
     stream = torch.cuda.current_stream()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
 
-    def step(events=None):
-        plan = hygt.Plan(at, ct, workspace=ws)
+    def step(k, events=None):
+        plan = hygt.Plan(at, cs[k % RING], workspace=ws)
         if events:
             events[0].record(stream)
-        plan.forward(xt, out=yt)
+        plan.forward(xs[k % RING], out=yt)
         if events:
             events[1].record(stream)
             events[2].record(stream)
@@ -195,16 +207,16 @@ def main():
             events[3].record(stream)
         return plan
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
-    plan = step()
+    plan = step(0)
     plan.check()
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(ev[i])
+        step(i, ev[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -216,7 +228,7 @@ def main():
     achieved = launch_bytes / (fwd_ms / 1e3) / 1e9
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
-    klt = _klt_comparison(torch, hygt, at, ct, xt, args.steps)
+    klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -237,7 +249,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "HyGT 8x8 blocks fwd+inv: 2^20 blocks, N=64, R=4, 35 classes, "
                                "AR(1) rho=0.9 sigma=40 int-valued FP32",
-                   "nblocks": NBLOCKS, "N": N, "rounds": ROUNDS, "classes": NCLASSES},
+                   "nblocks": NBLOCKS, "N": N, "rounds": ROUNDS, "classes": NCLASSES,
+                   "input_ring": RING},
         "step_hbm_gbps": step_gbps,
         "step_pct_peak": 100.0 * step_gbps / HBM_PEAK_GBPS,
         "fwd_ms": fwd_ms,

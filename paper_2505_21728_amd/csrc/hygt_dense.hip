@@ -32,6 +32,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 using lds_void_ptr = __attribute__((address_space(3))) void*;
@@ -148,8 +149,12 @@ __global__ __launch_bounds__(64 * kDenseWaves) void dense_kernel(
         const int b = 4 * i + lane / 16;
         const int q = (lane % 16) ^ (b & 15);
         const float4 f = L[i * 64 + lane];
-        if (bb[i] >= 0)
-            *reinterpret_cast<float4*>(y + static_cast<int64_t>(bb[i]) * kDenseN + q * 4) = f;
+        if (bb[i] >= 0) {
+            // non-temporal: outputs are not read again by this launch
+            const vf4 w = {f.x, f.y, f.z, f.w};
+            __builtin_nontemporal_store(w, reinterpret_cast<vf4*>(
+                                               y + static_cast<int64_t>(bb[i]) * kDenseN + q * 4));
+        }
     }
 }
 

@@ -262,6 +262,16 @@ __device__ __forceinline__ void gather_part(const float* __restrict__ x, float4*
     });
 }
 
+// Outputs are written with non-temporal stores: they are not read again by
+// this launch, and keeping them out of the caches leaves room for the inputs
+// (measured on MI355X: 146 -> 132 us for the 8x8 forward transform of 2^20
+// blocks, cache-cold inputs).
+__device__ __forceinline__ void store_nt(float* p, float4 f) {
+    typedef float vf4 __attribute__((ext_vector_type(4)));
+    const vf4 w = {f.x, f.y, f.z, f.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<vf4*>(p));
+}
+
 template <int D>
 __device__ __forceinline__ void scatter_part(float* __restrict__ y, const float4* L,
                                              const int* bb, int lane, int part) {
@@ -271,8 +281,7 @@ __device__ __forceinline__ void scatter_part(float* __restrict__ y, const float4
         const int b = i * G::BPI + lane / G::CHP;
         const int ch = part * G::CHP + ((lane % G::CHP) ^ swz<G::CHP>(b));
         const float4 f = L[i * 64 + lane];
-        if (bb[i] >= 0)
-            *reinterpret_cast<float4*>(y + static_cast<int64_t>(bb[i]) * G::N + ch * 4) = f;
+        if (bb[i] >= 0) store_nt(y + static_cast<int64_t>(bb[i]) * G::N + ch * 4, f);
     });
 }
 
