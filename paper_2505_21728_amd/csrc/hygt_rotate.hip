@@ -12,14 +12,17 @@
 // along bit 7 pair the two halves, which swap values through LDS in parts of
 // 16 per lane.
 //
-// Memory. A tile moves between HBM and registers through LDS in both
-// directions, so that every global access covers whole blocks (or whole
-// 128-byte halves of 8x8 blocks): each load or store instruction moves 16
-// bytes per lane for several blocks. The 16-byte chunks of a block are
-// rotated by an XOR swizzle in LDS so that the per-lane row reads and writes
-// hit distinct banks. Loads go straight to LDS (global_load_lds_dwordx4)
-// without passing through VGPRs. A tile goes through in parts of at most 8
-// chunks per block, so a wavefront needs only 8 KB of LDS.
+// Memory. Each lane loads its own block (for N = 256, its half of the block)
+// straight into registers, N / 4 loads of 16 bytes all in flight at once, so
+// the first passes start on the chunks that arrive first. The way out goes
+// through LDS: each lane writes its row, and the transposed slots go out so
+// that each store instruction writes whole blocks (or whole 128-byte halves
+// of 8x8 blocks), 16 bytes per lane; an XOR swizzle of the 16-byte chunks in
+// LDS keeps the row writes on distinct banks. A tile goes out in parts of at
+// most 8 chunks per block, so a wavefront needs only 8 KB of LDS. Stores are
+// non-temporal. Measured on MI355X with cache-cold inputs, direct loads beat
+// a gather through LDS (global_load_lds_dwordx4) by 4 to 6 us per 2^20 8x8
+// blocks, and non-temporal stores beat ordinary ones by 14 us.
 //
 // Scheduling. Each wavefront handles one tile, four per workgroup. The
 // lifting form needs no temporaries, so a wavefront fits in under 100 VGPRs
@@ -66,8 +69,6 @@ struct StaticFor {
         }
     }
 };
-
-using lds_void_ptr = __attribute__((address_space(3))) void*;
 
 constexpr int ins0(int j, int k) { return ((j >> k) << (k + 1)) | (j & ((1 << k) - 1)); }
 
@@ -207,7 +208,7 @@ __device__ __forceinline__ int valid_block(int b, int64_t nblocks) {
     return (b >= 0 && b < nblocks) ? b : -1;  // never touch memory outside x / y
 }
 
-// A tile moves between HBM and LDS in PARTS parts of CHP 16-byte chunks per
+// A tile goes out from registers through LDS in PARTS parts of CHP 16-byte chunks per
 // block (CHP = min(N/4, kChunksPerPart)); a wavefront's LDS image of one part
 // is 64 * CHP * 16 bytes.
 #ifndef HYGT_CHUNKS_PER_PART
@@ -240,32 +241,8 @@ __device__ __forceinline__ void instr_blocks(int* bb, int blk, int lane) {
     });
 }
 
-// Instruction i of part `part` fetches, for block b = i*BPI + lane/CHP, the chunk
-// part*CHP + ((lane%CHP) ^ swz(b)) of its row into LDS slot i*64 + lane, which
-// is b*CHP + (chunk-in-part ^ swz(b)). Rows are N floats apart; a lane's row
-// is the whole block, or for N = 256 the half that x and y point into.
-template <int D>
-__device__ __forceinline__ void gather_part(const float* __restrict__ x, float4* L,
-                                            const int* bb, int lane, int part) {
-    using G = TileGeo<D>;
-    StaticFor<0, G::CHP>::run([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        const int b = i * G::BPI + lane / G::CHP;
-        const int ch = part * G::CHP + ((lane % G::CHP) ^ swz<G::CHP>(b));
-#if defined(__HIP_DEVICE_COMPILE__)  // the LDS-DMA builtin exists only in the device pass
-        if (bb[i] >= 0)
-            __builtin_amdgcn_global_load_lds(x + static_cast<int64_t>(bb[i]) * G::N + ch * 4,
-                                             (lds_void_ptr)(L + i * 64), 16, 0, 0);
-#else
-        (void)b, (void)ch, (void)x, (void)L;
-#endif
-    });
-}
-
 // Outputs are written with non-temporal stores: they are not read again by
-// this launch, and keeping them out of the caches leaves room for the inputs
-// (measured on MI355X: 146 -> 132 us for the 8x8 forward transform of 2^20
-// blocks, cache-cold inputs).
+// this launch, and keeping them out of the caches leaves room for the inputs.
 __device__ __forceinline__ void store_nt(float* p, float4 f) {
     typedef float vf4 __attribute__((ext_vector_type(4)));
     const vf4 w = {f.x, f.y, f.z, f.w};
@@ -285,27 +262,22 @@ __device__ __forceinline__ void scatter_part(float* __restrict__ y, const float4
     });
 }
 
-// Brings part P of a tile into registers: gather into L, then each lane
-// reads its block's CHP chunks of the part.
-template <int D, int P>
-__device__ __forceinline__ void load_part(const float* __restrict__ x, float4* L, const int* bb,
-                                          float* v, int lane, int sw) {
+// Brings a lane's row (its block, or for N = 256 its half of the block)
+// into registers: V / 4 loads of 16 bytes, all in flight at once, so the
+// first passes can start on the chunks that arrive first.
+template <int D>
+__device__ __forceinline__ void load_row(const float* __restrict__ x, int blk, float* v) {
     using G = TileGeo<D>;
-    constexpr int CHP = G::CHP;
-    gather_part<D>(x, L, bb, lane, P);
-    // The DMA writes land in LDS asynchronously.
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    StaticFor<0, CHP>::run([&](auto qq) {
+    if (blk < 0) return;
+    const float4* src = reinterpret_cast<const float4*>(x + static_cast<int64_t>(blk) * G::N);
+    StaticFor<0, G::V / 4>::run([&](auto qq) {
         constexpr int q = decltype(qq)::value;
-        constexpr int e = 4 * (P * CHP + q);
-        const float4 f = L[lane * CHP + (q ^ sw)];
-        v[e + 0] = f.x;
-        v[e + 1] = f.y;
-        v[e + 2] = f.z;
-        v[e + 3] = f.w;
+        const float4 f = src[q];
+        v[4 * q + 0] = f.x;
+        v[4 * q + 1] = f.y;
+        v[4 * q + 2] = f.z;
+        v[4 * q + 3] = f.w;
     });
-    // A later DMA into L must not overtake these row reads.
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
 // Writes part P of a tile back: each lane writes its block's CHP chunks of
@@ -377,18 +349,11 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
     float4* L = lds[wv];
     int blk[T];
     float v[T][G::V];
-    {
-        const int sw = swz<CHP>(lane);
-        StaticFor<0, T>::run([&](auto uu) {
-            constexpr int u = decltype(uu)::value;
-            blk[u] = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
-            int bb[CHP];
-            instr_blocks<D>(bb, blk[u], lane);
-            StaticFor<0, G::PARTS>::run([&](auto pp) {
-                load_part<D, decltype(pp)::value>(xh, L, bb, v[u], lane, sw);
-            });
-        });
-    }
+    StaticFor<0, T>::run([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        blk[u] = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
+        load_row<D>(xh, blk[u], v[u]);
+    });
 
     const size_t passes = static_cast<size_t>(rounds) * D;
     const size_t table = static_cast<size_t>(DIR) * nclasses + c;
