@@ -31,9 +31,10 @@
 // class over the whole batch, so that the wavefronts of a compute unit pair
 // mostly share one class and its table stays in their scalar cache. The
 // counting sort takes two launches over chunks of consecutive blocks: the
-// first counts the classes of each chunk (beside the table builders), the
-// second gives every chunk its start inside each class from the counts of
-// the chunks before it and scatters the block ids into the class's tiles.
+// first counts the classes of each chunk, the second gives every chunk its
+// start inside each class from the counts of the chunks before it and
+// scatters the block ids into the class's tiles, while other workgroups of
+// the same launch build the multiplier tables.
 
 #include <algorithm>
 #include <cmath>
@@ -53,22 +54,21 @@ __device__ __forceinline__ int insert_zero_bit(int j, int k) {
 constexpr int kAngleBatch = 2048;
 // Entries of the per-chunk class counts cached in LDS by the placing kernel.
 constexpr int kCountsCache = 16384;
-// Blocks whose class indices one thread loads at once.
-constexpr int kUnroll = 4;
+// Blocks whose class indices one thread loads at once (a whole chunk of
+// kMinChunk blocks in one round of loads).
+constexpr int kUnroll = static_cast<int>(kMinChunk / kPlanThreads);
 
-// LDS of the first plan launch: a table builder or a chunk counter.
+// LDS of a table builder (a workgroup of the placing launch).
+struct TableShared {
+    int sign[256];
+    float tanh_phi[kAngleBatch];    // tan(phi/2) of the batch's angles (cos for bit 7)
+    float sin_phi[kAngleBatch];     // sin(phi) (sin theta for bit 7)
+    signed char flip[kAngleBatch];  // -1 where |theta| > pi/2
+};
+
+// LDS of a chunk counter (the counting launch).
 struct CountShared {
-    union {
-        struct {  // table builders
-            int sign[256];
-            float tanh_phi[kAngleBatch];  // tan(phi/2) of the batch's angles (cos for bit 7)
-            float sin_phi[kAngleBatch];   // sin(phi) (sin theta for bit 7)
-            signed char flip[kAngleBatch];  // -1 where |theta| > pi/2
-        } t;
-        struct {  // chunk counting
-            int hist[HYGT_MAX_CLASSES];
-        } c;
-    };
+    int hist[HYGT_MAX_CLASSES];
     int flag;
 };
 
@@ -92,7 +92,9 @@ __host__ __device__ inline bool place_counts_cached(int64_t nchunks, int nclasse
 __host__ __device__ inline size_t place_lds_bytes(int64_t nchunks, int nclasses) {
     const size_t cached = place_counts_cached(nchunks, nclasses)
                               ? static_cast<size_t>(nchunks) * nclasses : 0;
-    return (cached + 4 * static_cast<size_t>(nclasses) + 1 + kPlanThreads) * sizeof(int);
+    const size_t place = (cached + 4 * static_cast<size_t>(nclasses) + 1 + kPlanThreads) *
+                         sizeof(int);
+    return place > sizeof(TableShared) ? place : sizeof(TableShared);
 }
 
 __device__ inline PlaceLds place_lds(int* base, int64_t nchunks, int nclasses) {
@@ -110,7 +112,7 @@ __device__ inline PlaceLds place_lds(int* base, int64_t nchunks, int nclasses) {
 // Multiplier table of one (direction, class); see the file comment. The
 // FP64 conversion of a batch of angles runs in parallel; only the sign walk
 // through the passes is sequential.
-__device__ void build_table(CountShared& sh, int dir, int c, const float* __restrict__ angles,
+__device__ void build_table(TableShared& sh, int dir, int c, const float* __restrict__ angles,
                             int log2n, int rounds, int nclasses, float* __restrict__ coef,
                             float* __restrict__ signs, int32_t* __restrict__ modes) {
     const int tid = threadIdx.x;
@@ -120,7 +122,7 @@ __device__ void build_table(CountShared& sh, int dir, int c, const float* __rest
     const size_t table = static_cast<size_t>(dir) * nclasses + c;
     float* cbase = coef + table * passes * n;
     const int batch_passes = kAngleBatch / half;
-    for (int i = tid; i < n; i += blockDim.x) sh.t.sign[i] = 1;
+    for (int i = tid; i < n; i += blockDim.x) sh.sign[i] = 1;
     for (int p0 = 0; p0 < passes; p0 += batch_passes) {
         const int p1 = min(passes, p0 + batch_passes);
         __syncthreads();
@@ -136,9 +138,9 @@ __device__ void build_table(CountShared& sh, int dir, int c, const float* __rest
                 angles[((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + j]);
             if (dir) th = -th;
             if (k >= kLaneBits) {  // (cos, sin) form, no reduction
-                sh.t.tanh_phi[e] = static_cast<float>(cos(th));
-                sh.t.sin_phi[e] = static_cast<float>(sin(th));
-                sh.t.flip[e] = 1;
+                sh.tanh_phi[e] = static_cast<float>(cos(th));
+                sh.sin_phi[e] = static_cast<float>(sin(th));
+                sh.flip[e] = 1;
                 continue;
             }
             // G(th) = f * G(phi) with |phi| <= pi/2
@@ -147,9 +149,9 @@ __device__ void build_table(CountShared& sh, int dir, int c, const float* __rest
             signed char f = 1;
             if (phi > pi / 2) { phi -= pi; f = -1; }
             else if (phi < -pi / 2) { phi += pi; f = -1; }
-            sh.t.tanh_phi[e] = static_cast<float>(tan(0.5 * phi));
-            sh.t.sin_phi[e] = static_cast<float>(sin(phi));
-            sh.t.flip[e] = f;
+            sh.tanh_phi[e] = static_cast<float>(tan(0.5 * phi));
+            sh.sin_phi[e] = static_cast<float>(sin(phi));
+            sh.flip[e] = f;
         }
         __syncthreads();
         for (int p = p0; p < p1; ++p) {
@@ -159,22 +161,22 @@ __device__ void build_table(CountShared& sh, int dir, int c, const float* __rest
                 const int e = (p - p0) * half + tid;
                 const int m = insert_zero_bit(tid, k);
                 const int nn = m + (1 << k);
-                const int sm = sh.t.sign[m];
-                const int sq = sh.t.sign[nn];
-                const int f = sh.t.flip[e];
+                const int sm = sh.sign[m];
+                const int sq = sh.sign[nn];
+                const int f = sh.flip[e];
                 // a pair whose stored signs differ is rotated by -phi
                 const float g = sm == sq ? 1.0f : -1.0f;
                 float* cp = cbase + static_cast<size_t>(p) * n;
                 if (k >= kLaneBits) {
                     // stored (sm a, sq b) -> (sm a', sq b'): the sine is
                     // multiplied by sm * sq, the signs stay
-                    cp[2 * tid + 0] = sh.t.tanh_phi[e];
-                    cp[2 * tid + 1] = g * sh.t.sin_phi[e];
+                    cp[2 * tid + 0] = sh.tanh_phi[e];
+                    cp[2 * tid + 1] = g * sh.sin_phi[e];
                 } else {
-                    cp[2 * tid + 0] = g * sh.t.tanh_phi[e];
-                    cp[2 * tid + 1] = -g * sh.t.sin_phi[e];
-                    sh.t.sign[m] = f * sm;
-                    sh.t.sign[nn] = sm == sq ? f * sm : -f * sm;
+                    cp[2 * tid + 0] = g * sh.tanh_phi[e];
+                    cp[2 * tid + 1] = -g * sh.sin_phi[e];
+                    sh.sign[m] = f * sm;
+                    sh.sign[nn] = sm == sq ? f * sm : -f * sm;
                 }
             }
             __syncthreads();
@@ -182,8 +184,8 @@ __device__ void build_table(CountShared& sh, int dir, int c, const float* __rest
     }
     int neg = 0;
     for (int i = tid; i < n; i += blockDim.x) {
-        signs[table * n + i] = static_cast<float>(sh.t.sign[i]);
-        neg |= sh.t.sign[i] < 0;
+        signs[table * n + i] = static_cast<float>(sh.sign[i]);
+        neg |= sh.sign[i] < 0;
     }
     neg = __syncthreads_or(neg);
     if (tid == 0) modes[table] = neg ? 1 : 0;
@@ -222,7 +224,7 @@ __device__ void count_chunk(CountShared& sh, int64_t k, const int32_t* __restric
     const int tid = threadIdx.x;
     const int64_t start = k * chunk;
     const int cnt = static_cast<int>(min<int64_t>(chunk, nblocks - start));
-    for (int c = tid; c < nclasses; c += blockDim.x) sh.c.hist[c] = 0;
+    for (int c = tid; c < nclasses; c += blockDim.x) sh.hist[c] = 0;
     if (tid == 0) sh.flag = 0;
     __syncthreads();
     if (cls != nullptr) {
@@ -240,59 +242,71 @@ __device__ void count_chunk(CountShared& sh, int64_t k, const int32_t* __restric
                 const int i = i0 + u * static_cast<int>(blockDim.x);
                 if (i >= cnt) break;
                 if (cv[u] >= 0 && cv[u] < nclasses)
-                    atomicAdd(&sh.c.hist[cv[u]], 1);
+                    atomicAdd(&sh.hist[cv[u]], 1);
                 else
                     sh.flag = 1;
             }
         }
     } else if (tid == 0) {
-        sh.c.hist[0] = cnt;
+        sh.hist[0] = cnt;
     }
     __syncthreads();
     for (int c = tid; c < nclasses; c += blockDim.x)
-        counts[k * nclasses + c] = sh.c.hist[c];
+        counts[k * nclasses + c] = sh.hist[c];
     if (tid == 0) chunk_err[k] = sh.flag;
 }
 
-// Launch A: workgroups [0, 2C) build the multiplier tables of (direction,
-// class), the next nchunks workgroups count one chunk each.
+// Launch A: workgroup k counts chunk k.
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(
-    const int32_t* __restrict__ cls, int64_t nblocks, const float* __restrict__ angles,
-    int log2n, int rounds, int nclasses, int64_t nchunks, int64_t chunk,
-    PlanHeader* __restrict__ hdr, int32_t* __restrict__ chunk_err,
-    int32_t* __restrict__ counts, int32_t* __restrict__ modes, float* __restrict__ coef,
-    float* __restrict__ signs) {
+    const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
+    int64_t chunk, PlanHeader* __restrict__ hdr, int32_t* __restrict__ chunk_err,
+    int32_t* __restrict__ counts) {
     __shared__ CountShared sh;
-    const int64_t wg = blockIdx.x;
-    if (wg < 2 * nclasses) {
-        build_table(sh, static_cast<int>(wg / nclasses), static_cast<int>(wg % nclasses), angles,
-                    log2n, rounds, nclasses, coef, signs, modes);
-        return;
-    }
-    const int64_t k = wg - 2 * nclasses;
+    const int64_t k = blockIdx.x;
     if (k == 0 && threadIdx.x == 0) hdr->nchunks = static_cast<int32_t>(nchunks);
     count_chunk(sh, k, cls, nblocks, chunk, nclasses, counts, chunk_err);
 }
 
-// Launch B: chunk k places its blocks. Class c's blocks fill tiles
-// tile_base[c] .. in chunk order; inside a chunk their order is that of the
-// LDS counters (any order gives the same results, block by block).
+// Launch B: workgroups [0, 2C) build the multiplier tables of (direction,
+// class), which need nothing from launch A, so they run beside the placing
+// workgroups instead of before them; workgroup 2C + k places chunk k. Class
+// c's blocks fill tiles tile_base[c] .. in chunk order; inside a chunk their
+// order is that of the LDS counters (any order gives the same results,
+// block by block).
 __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
     int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
-    int32_t* __restrict__ tile_class, int32_t* __restrict__ perm) {
+    int32_t* __restrict__ tile_class, int32_t* __restrict__ perm,
+    const float* __restrict__ angles, int log2n, int rounds, int32_t* __restrict__ modes,
+    float* __restrict__ coef, float* __restrict__ signs) {
     extern __shared__ __align__(16) int place_dyn[];
+    if (blockIdx.x < 2 * nclasses) {
+        const int wg = static_cast<int>(blockIdx.x);
+        build_table(*reinterpret_cast<TableShared*>(place_dyn), wg / nclasses, wg % nclasses,
+                    angles, log2n, rounds, nclasses, coef, signs, modes);
+        return;
+    }
     const PlaceLds sh = place_lds(place_dyn, nchunks, nclasses);
     const int tid = threadIdx.x;
-    const int64_t k = blockIdx.x;
+    const int64_t k = blockIdx.x - 2 * static_cast<int64_t>(nclasses);
     const int64_t ncounts = nchunks * nclasses;
     const bool cached = place_counts_cached(nchunks, nclasses);
+    // The first round of this chunk's class indices, loaded now so that their
+    // latency overlaps the count reduction below.
+    const int64_t start = k * chunk;
+    const int cnt = static_cast<int>(min<int64_t>(chunk, nblocks - start));
+    int cv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int i = tid + u * static_cast<int>(blockDim.x);
+        cv[u] = (i < cnt && cls != nullptr) ? cls[start + i] : 0;
+    }
     if (cached) {
-        // 16-byte loads (counts starts 256-byte aligned), several in flight
+        // 16-byte loads (counts starts 256-byte aligned), all in flight
         const int64_t n4 = ncounts / 4;
         const int4* c4 = reinterpret_cast<const int4*>(counts);
         int4* s4 = reinterpret_cast<int4*>(sh.counts);  // sh.counts is at the LDS base
-#pragma unroll 4
+#pragma unroll 16
         for (int64_t e = tid; e < n4; e += blockDim.x) s4[e] = c4[e];
         for (int64_t e = n4 * 4 + tid; e < ncounts; e += blockDim.x) sh.counts[e] = counts[e];
     }
@@ -338,15 +352,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     if (tid == 0) sh.tile_base[nclasses] = ntiles;
     __syncthreads();
     // Block ids of this chunk into their classes' tiles.
-    const int64_t start = k * chunk;
-    const int cnt = static_cast<int>(min<int64_t>(chunk, nblocks - start));
     const int step = static_cast<int>(blockDim.x) * kUnroll;
     for (int i0 = tid; i0 < cnt; i0 += step) {
-        int cv[kUnroll];
+        if (i0 != tid) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int i = i0 + u * static_cast<int>(blockDim.x);
-            cv[u] = (i < cnt && cls != nullptr) ? cls[start + i] : 0;
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = i0 + u * static_cast<int>(blockDim.x);
+                cv[u] = (i < cnt && cls != nullptr) ? cls[start + i] : 0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -389,10 +402,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
                        const float* angles, int nclasses, const WsLayout& l,
                        const WsPtrs& p, hipStream_t stream) {
-    hipLaunchKernelGGL(plan_count_kernel, dim3(static_cast<unsigned>(2 * nclasses + l.nchunks)),
-                       dim3(kPlanThreads), 0, stream, cls, nblocks, angles, log2n, rounds,
-                       nclasses, l.nchunks, l.chunk, p.hdr, p.chunk_err, p.counts, p.modes,
-                       p.coef, p.signs);
+    hipLaunchKernelGGL(plan_count_kernel, dim3(static_cast<unsigned>(l.nchunks)),
+                       dim3(kPlanThreads), 0, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
+                       p.hdr, p.chunk_err, p.counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = place_lds_bytes(l.nchunks, nclasses);
@@ -402,9 +414,10 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
                                 static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(plan_place_kernel, dim3(static_cast<unsigned>(l.nchunks)),
+    hipLaunchKernelGGL(plan_place_kernel, dim3(static_cast<unsigned>(2 * nclasses + l.nchunks)),
                        dim3(kPlanThreads), lds, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
-                       l.max_tiles, p.counts, p.tile_class, p.perm);
+                       l.max_tiles, p.counts, p.tile_class, p.perm, angles, log2n, rounds,
+                       p.modes, p.coef, p.signs);
     return hipGetLastError();
 }
 
