@@ -107,28 +107,31 @@ class Plan:
                  f"x must be [{self.nblocks}, {self.n}]")
         _require(x.is_contiguous(), "x must be contiguous")
 
-    def apply(self, x, direction: int, out=None):
+    def apply(self, x, direction: int, out=None, stream=None):
+        """Enqueues the transform on `stream` (default: the plan's stream, else
+        the current one). Work on another stream than the plan's must be
+        ordered after the plan by the caller (events)."""
         torch = _torch()
         self._check_x(x)
         if out is None:
             out = torch.empty_like(x)
         else:
             self._check_x(out)
+        s = stream if stream is not None else self._stream
         with torch.cuda.device(self.device):
             st = _abi.hygt_apply(x.data_ptr(), out.data_ptr(), self.nblocks, self.log2n,
                                  self.rounds, self.nclasses, direction,
-                                 self.workspace.data_ptr(), self.ws_bytes,
-                                 _stream_handle(self._stream))
+                                 self.workspace.data_ptr(), self.ws_bytes, _stream_handle(s))
         _abi._check(st, "hygt_apply")
         return out
 
-    def forward(self, x, out=None):
+    def forward(self, x, out=None, stream=None):
         """y[b] = T_{cls[b]} x[b] (eq. (5))."""
-        return self.apply(x, HYGT_FORWARD, out)
+        return self.apply(x, HYGT_FORWARD, out, stream)
 
-    def inverse(self, x, out=None):
+    def inverse(self, x, out=None, stream=None):
         """y[b] = T_{cls[b]}^T x[b] (eq. (6) and (9))."""
-        return self.apply(x, HYGT_INVERSE, out)
+        return self.apply(x, HYGT_INVERSE, out, stream)
 
     def dense(self, x, mats, out=None):
         """y[b] = M_{cls[b]} x[b] with BF16 matrices mats [C, N, N] on the
