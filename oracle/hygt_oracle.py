@@ -53,6 +53,9 @@ __all__ = [
     "dense_transform",
     "rel_l2_per_block",
     "rel_l2_global",
+    "class_log_variance_loss",
+    "class_log_variance_grad",
+    "backward",
 ]
 
 
@@ -281,6 +284,84 @@ def dense_transform(x, cls, mats) -> np.ndarray:
     for b in range(x.shape[0]):
         y[b] = mats[cls[b]] @ x[b]
     return y
+
+
+# ---------------------------------------------------------------------------
+# Angle gradients for the parameter optimisation of Sec. V
+# ---------------------------------------------------------------------------
+
+def class_log_variance_loss(y, cls, nclasses: int, eps: float = 1e-6) -> float:
+    """sum over classes c and coefficients i of log(var_{c,i} + eps).
+
+    Sec. V rates a transform by the variances of its coefficients, the
+    diagonal of T Phi T^T (eq. (10)), under the high-rate model of eq. (11),
+    in which the rate of a coefficient grows with the log of its variance.
+    Here var_{c,i} is the mean of y_{b,i}^2 over the blocks b of class c (the
+    variances with Phi estimated from those blocks). A class with no blocks
+    adds nothing.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    cls = np.asarray(cls, dtype=np.int64)
+    total = 0.0
+    for c in range(nclasses):
+        rows = y[cls == c]
+        if rows.shape[0] == 0:
+            continue
+        var = np.mean(rows * rows, axis=0)
+        total += float(np.sum(np.log(var + eps)))
+    return total
+
+
+def class_log_variance_grad(y, cls, nclasses: int, eps: float = 1e-6) -> np.ndarray:
+    """dL/dy of class_log_variance_loss: 2 y_{b,i} / (n_c (var_{c,i} + eps))."""
+    y = np.asarray(y, dtype=np.float64)
+    cls = np.asarray(cls, dtype=np.int64)
+    g = np.zeros_like(y)
+    for c in range(nclasses):
+        sel = cls == c
+        n_c = int(np.count_nonzero(sel))
+        if n_c == 0:
+            continue
+        var = np.mean(y[sel] * y[sel], axis=0)
+        g[sel] = 2.0 * y[sel] / (n_c * (var + eps))
+    return g
+
+
+def backward(y, gy, cls, angles):
+    """Reverse-mode derivative of forward().
+
+    Given the outputs y = forward(x, cls, angles) and gy = dL/dy, returns
+    (gx, gangles): gx = dL/dx for every block and gangles = dL/dangles with
+    the same layout as angles, summed over the blocks of each class.
+
+    The passes are walked in reverse order (last round first, pass d-1 first
+    inside it). Each pass's inputs are recovered from its outputs by the
+    inverse rotation (eq. (9)) instead of being stored. For one rotation
+    y_m = c x_m + s x_n, y_n = -s x_m + c x_n:
+        dy_m/dtheta = y_n and dy_n/dtheta = -y_m, so dL/dtheta = g_m y_n - g_n y_m;
+        (dL/dx_m, dL/dx_n) = (c g_m - s g_n, s g_m + c g_n), the inverse rotation of g.
+    """
+    y, cls, angles, rounds, d = _check(y, cls, angles)
+    g = np.array(gy, dtype=np.float64, copy=True)
+    if g.shape != y.shape:
+        raise ValueError("gy must have the shape of y")
+    v = y.copy()
+    gangles = np.zeros_like(angles)
+    for r in reversed(range(rounds)):
+        for k in reversed(range(d)):
+            m, n = pair_indices(d, k)
+            theta = angles[cls, r, k, :]
+            c = np.cos(theta)
+            s = np.sin(theta)
+            contrib = g[:, m] * v[:, n] - g[:, n] * v[:, m]      # [B, N/2]
+            np.add.at(gangles[:, r, k, :], cls, contrib)
+            ym, yn = v[:, m].copy(), v[:, n].copy()
+            v[:, m] = c * ym - s * yn
+            v[:, n] = s * ym + c * yn
+            gm, gn = g[:, m].copy(), g[:, n].copy()
+            g[:, m] = c * gm - s * gn
+            g[:, n] = s * gm + c * gn
+    return g, gangles
 
 
 # ---------------------------------------------------------------------------

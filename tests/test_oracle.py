@@ -371,3 +371,137 @@ def test_pins_catch_mutant(name):
         except AssertionError:
             failures += 1
     assert failures >= 1, f"no pin caught mutant {name}"
+
+
+# ---------------------------------------------------------------------------
+# Backward (angle and input gradients of the Sec. V objective)
+# ---------------------------------------------------------------------------
+
+def _fd_loss_grads(x, cls, ang, nclasses, angle_idx=None, x_idx=None, h=1e-6, backward=None):
+    """Central differences of the FP64 loss, compared with backward()."""
+    bwd = backward or orc.backward
+
+    def loss(a, xx):
+        return orc.class_log_variance_loss(orc.forward(xx, cls, a), cls, nclasses)
+
+    y = orc.forward(x, cls, ang)
+    gy = orc.class_log_variance_grad(y, cls, nclasses)
+    gx, ga = bwd(y, gy, cls, ang)
+    angle_idx = list(np.ndindex(ang.shape)) if angle_idx is None else angle_idx
+    x_idx = list(np.ndindex(x.shape)) if x_idx is None else x_idx
+    errs = []
+    for idx in angle_idx:
+        a1, a2 = ang.copy(), ang.copy()
+        a1[idx] += h
+        a2[idx] -= h
+        errs.append(abs((loss(a1, x) - loss(a2, x)) / (2 * h) - ga[idx]))
+    for idx in x_idx:
+        x1, x2 = x.copy(), x.copy()
+        x1[idx] += h
+        x2[idx] -= h
+        errs.append(abs((loss(ang, x1) - loss(ang, x2)) / (2 * h) - gx[idx]))
+    scale = max(np.abs(ga).max(), np.abs(gx).max())
+    return max(errs) / scale
+
+
+@pytest.mark.parametrize("d,rounds,nclasses,nb", [(1, 3, 2, 10), (2, 2, 2, 12), (3, 2, 3, 30),
+                                                  (4, 1, 2, 40)])
+def test_backward_matches_finite_differences(d, rounds, nclasses, nb):
+    """Every angle and every input of a small batch: the gradient equals the
+    central difference of the FP64 loss."""
+    rng = np.random.default_rng(10 * d + rounds)
+    ang = rng.uniform(-math.pi, math.pi, (nclasses, rounds, d, 1 << (d - 1)))
+    x = 10 * rng.standard_normal((nb, 1 << d))
+    cls = rng.integers(0, nclasses, nb)
+    assert _fd_loss_grads(x, cls, ang, nclasses) < 1e-7
+
+
+def test_backward_fd_on_256_ar1_blocks():
+    """256 8x8 AR(1) blocks, 35 classes, R = 4: 40 sampled angles and 40
+    sampled inputs against central differences in FP64."""
+    from paper_2505_21728_amd import synth
+
+    ang = synth.angles(35, 4, 6).astype(np.float64)
+    x = synth.ar1_blocks(256, 8, seed=5).astype(np.float64)
+    cls = synth.classes(256, 35, seed=6)
+    rng = np.random.default_rng(3)
+    present = np.unique(cls)
+    aidx = [(int(rng.choice(present)), int(rng.integers(4)), int(rng.integers(6)),
+             int(rng.integers(32))) for _ in range(40)]
+    xidx = [(int(rng.integers(256)), int(rng.integers(64))) for _ in range(40)]
+    assert _fd_loss_grads(x, cls, ang, 35, aidx, xidx, h=1e-5) < 1e-7
+
+
+def test_backward_n2_closed_form():
+    """N = 2, one rotation, L = y_0: dL/dtheta = -sin x_0 + cos x_1 and
+    dL/dx = (cos, sin)."""
+    th, x0, x1 = 0.7, 1.3, -0.4
+    x = np.array([[x0, x1]])
+    ang = np.array([[[[th]]]])
+    y = orc.forward(x, None, ang)
+    gx, ga = orc.backward(y, np.array([[1.0, 0.0]]), None, ang)
+    assert np.isclose(ga[0, 0, 0, 0], -math.sin(th) * x0 + math.cos(th) * x1, rtol=0, atol=1e-15)
+    assert np.allclose(gx[0], [math.cos(th), math.sin(th)], rtol=0, atol=1e-15)
+
+
+def test_backward_input_gradient_is_the_inverse():
+    """dL/dx = T^T dL/dy, and T^T = T^-1 (eq. (6), (9))."""
+    rng = np.random.default_rng(4)
+    ang = rng.uniform(-math.pi, math.pi, (3, 2, 4, 8))
+    x = rng.standard_normal((50, 16))
+    cls = rng.integers(0, 3, 50)
+    gy = rng.standard_normal((50, 16))
+    gx, _ = orc.backward(orc.forward(x, cls, ang), gy, cls, ang)
+    assert np.allclose(gx, orc.inverse(gy, cls, ang), rtol=0, atol=1e-12)
+
+
+def test_loss_gradient_and_empty_classes():
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((9, 4))
+    cls = np.array([0, 0, 2, 2, 2, 0, 2, 0, 0])     # class 1 and 3 empty
+    L = orc.class_log_variance_loss(y, cls, 4)
+    by_hand = sum(float(np.sum(np.log(np.mean(y[cls == c] ** 2, axis=0) + 1e-6)))
+                  for c in (0, 2))
+    assert L == pytest.approx(by_hand, rel=1e-14)
+    g = orc.class_log_variance_grad(y, cls, 4)
+    h = 1e-6
+    for idx in np.ndindex(y.shape):
+        y1, y2 = y.copy(), y.copy()
+        y1[idx] += h
+        y2[idx] -= h
+        fd = (orc.class_log_variance_loss(y1, cls, 4) - orc.class_log_variance_loss(y2, cls, 4))
+        assert abs(fd / (2 * h) - g[idx]) < 1e-7
+
+
+def _mutant_backward(flip_angle_sign=False, recover_with_forward=False):
+    def bwd(y, gy, cls, angles):
+        y, cls, angles, rounds, d = orc._check(y, cls, angles)
+        g = np.array(gy, dtype=np.float64, copy=True)
+        v = y.copy()
+        ga = np.zeros_like(angles)
+        for r in reversed(range(rounds)):
+            for k in reversed(range(d)):
+                m, n = orc.pair_indices(d, k)
+                th = angles[cls, r, k, :]
+                c, s = np.cos(th), np.sin(th)
+                contrib = g[:, m] * v[:, n] - g[:, n] * v[:, m]
+                np.add.at(ga[:, r, k, :], cls, -contrib if flip_angle_sign else contrib)
+                sv = -s if recover_with_forward else s
+                ym, yn = v[:, m].copy(), v[:, n].copy()
+                v[:, m] = c * ym - sv * yn
+                v[:, n] = sv * ym + c * yn
+                gm, gn = g[:, m].copy(), g[:, n].copy()
+                g[:, m] = c * gm - s * gn
+                g[:, n] = s * gm + c * gn
+        return g, ga
+    return bwd
+
+
+@pytest.mark.parametrize("mutant", ["flip_angle_sign", "recover_with_forward"])
+def test_fd_pin_catches_backward_mutants(mutant):
+    rng = np.random.default_rng(8)
+    ang = rng.uniform(-math.pi, math.pi, (2, 2, 3, 4))
+    x = 5 * rng.standard_normal((20, 8))
+    cls = rng.integers(0, 2, 20)
+    bwd = _mutant_backward(**{mutant: True})
+    assert _fd_loss_grads(x, cls, ang, 2, backward=bwd) > 1e-4
