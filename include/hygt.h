@@ -134,6 +134,28 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks,
                  int log2n, int rounds, const float* angles, int nclasses,
                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Largest block length (log2) supported by hygt_backward(). */
+#define HYGT_BACKWARD_MAX_LOG2N 6
+
+/* Reverse-mode derivative of hygt_apply(HYGT_FORWARD), for the parameter
+ * optimisation of Sec. V (a gradient step on the angles): given the forward
+ * outputs y = T_c x and gy = dL/dy, writes
+ *   gx       dL/dx = T_c^T gy for every block   [nblocks][N] float32;
+ *   gangles  dL/dangles, summed over the blocks of each class
+ *            [nclasses][rounds][log2n][N/2] float32 (same layout as angles,
+ *            overwritten; classes without blocks get zeros).
+ * Nothing from the forward call is needed but y: each pass's inputs are
+ * recovered from its outputs by the inverse rotation (eq. (9)). For one
+ * rotation, dL/dtheta = g_m y_n - g_n y_m. The workspace must hold a plan for
+ * these sizes, classes and angles (hygt_plan()); this call also writes a
+ * (cos, sin) table into it, so it must not overlap other calls on the same
+ * workspace. Alignment as for hygt_apply(); gx may be gy (in place) but not
+ * y. log2n <= HYGT_BACKWARD_MAX_LOG2N. The per-class sums are FP32 atomic
+ * additions, so their last bits can differ from run to run. */
+int hygt_backward(const float* y, const float* gy, float* gx, float* gangles, int64_t nblocks,
+                  int log2n, int rounds, const float* angles, int nclasses,
+                  void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Block length (log2) supported by hygt_dense_apply(). */
 #define HYGT_DENSE_LOG2N 6
 

@@ -16,10 +16,11 @@ from __future__ import annotations
 import math
 
 from . import _abi
-from ._abi import (HYGT_DENSE_LOG2N, HYGT_FORWARD, HYGT_INVERSE, HYGT_MAX_BLOCKS,
-                   HYGT_MAX_CLASSES, HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS, HygtError)
+from ._abi import (HYGT_BACKWARD_MAX_LOG2N, HYGT_DENSE_LOG2N, HYGT_FORWARD, HYGT_INVERSE,
+                   HYGT_MAX_BLOCKS, HYGT_MAX_CLASSES, HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS,
+                   HygtError)
 
-__all__ = ["Plan", "forward", "inverse", "workspace_bytes", "HygtError",
+__all__ = ["Plan", "forward", "inverse", "transform", "workspace_bytes", "HygtError",
            "HYGT_FORWARD", "HYGT_INVERSE"]
 
 
@@ -157,6 +158,37 @@ class Plan:
         _abi._check(st, "hygt_dense_apply")
         return out
 
+    def backward(self, y, gy, angles, gx=None, gangles=None, stream=None):
+        """Reverse-mode derivative of forward(): from the forward outputs y and
+        gy = dL/dy, returns (gx, gangles) with gx = dL/dx = T^T gy and
+        gangles = dL/dangles summed over each class's blocks. `angles` must be
+        the tensor this plan was built from. N <= 64."""
+        torch = _torch()
+        self._check_x(y)
+        self._check_x(gy)
+        _require(self.log2n <= HYGT_BACKWARD_MAX_LOG2N,
+                 f"backward supports N <= {1 << HYGT_BACKWARD_MAX_LOG2N}")
+        _require(isinstance(angles, torch.Tensor) and angles.dtype == torch.float32 and
+                 angles.device == self.device and angles.is_contiguous() and
+                 tuple(angles.shape) == (self.nclasses, self.rounds, self.log2n, self.n // 2),
+                 "angles must be the plan's [nclasses, rounds, log2n, N/2] float32 tensor")
+        if gx is None:
+            gx = torch.empty_like(y)
+        else:
+            self._check_x(gx)
+        if gangles is None:
+            gangles = torch.empty_like(angles)
+        _require(gangles.shape == angles.shape and gangles.dtype == torch.float32 and
+                 gangles.is_contiguous() and gangles.device == self.device, "bad gangles")
+        s = stream if stream is not None else self._stream
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_backward(y.data_ptr(), gy.data_ptr(), gx.data_ptr(),
+                                    gangles.data_ptr(), self.nblocks, self.log2n, self.rounds,
+                                    angles.data_ptr(), self.nclasses, self.workspace.data_ptr(),
+                                    self.ws_bytes, _stream_handle(s))
+        _abi._check(st, "hygt_backward")
+        return gx, gangles
+
     def check(self):
         """Synchronises and raises HygtError if a class index was out of range."""
         torch = _torch()
@@ -179,3 +211,40 @@ def inverse(x, cls, angles, out=None):
 def num_angles(n: int, rounds: int) -> int:
     """R * N * log2(N) / 2 angles per class (Sec. IV)."""
     return rounds * n * int(math.log2(n)) // 2
+
+
+def _function_class():
+    torch = _torch()
+
+    class HyGTTransform(torch.autograd.Function):
+        """y = T_{cls} x with gradients for x and the angles (Sec. V
+        optimisation). The backward runs the HIP backward kernel; nothing but
+        y is kept from the forward."""
+
+        @staticmethod
+        def forward(ctx, x, angles, cls):
+            plan = Plan(angles, cls, nblocks=x.shape[0])
+            y = plan.forward(x.contiguous())
+            ctx.plan = plan
+            ctx.save_for_backward(y, angles)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            y, angles = ctx.saved_tensors
+            gx, gangles = ctx.plan.backward(y, gy.contiguous(), angles)
+            return gx, gangles, None
+
+    return HyGTTransform
+
+
+_FN = None
+
+
+def transform(x, angles, cls):
+    """Differentiable y[b] = T_{cls[b]} x[b] (x [B, N] and angles
+    [C, R, log2N, N/2] float32 on the GPU, cls [B] int32)."""
+    global _FN
+    if _FN is None:
+        _FN = _function_class()
+    return _FN.apply(x, angles, cls)

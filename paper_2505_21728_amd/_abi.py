@@ -28,6 +28,7 @@ HYGT_MAX_ROUNDS = 64
 HYGT_MAX_CLASSES = 4096
 HYGT_MAX_BLOCKS = 2147483647
 HYGT_DENSE_LOG2N = 6
+HYGT_BACKWARD_MAX_LOG2N = 6
 
 # Every exported symbol with its (restype, argtypes).
 _c = ctypes
@@ -43,6 +44,9 @@ _SIGNATURES = {
     "hygt_inverse": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int,
                                 _c.c_int, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_size_t,
                                 _c.c_void_p]),
+    "hygt_backward": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                 _c.c_int, _c.c_int, _c.c_void_p, _c.c_int, _c.c_void_p,
+                                 _c.c_size_t, _c.c_void_p]),
     "hygt_dense_apply": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
                                     _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_size_t,
                                     _c.c_void_p]),
@@ -122,6 +126,12 @@ def hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, ncla
                  ws_bytes, stream) -> int:
     return load().hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr,
                                nclasses, ws_ptr, ws_bytes, stream)
+
+
+def hygt_backward(y_ptr, gy_ptr, gx_ptr, ga_ptr, nblocks, log2n, rounds, angles_ptr, nclasses,
+                  ws_ptr, ws_bytes, stream) -> int:
+    return load().hygt_backward(y_ptr, gy_ptr, gx_ptr, ga_ptr, nblocks, log2n, rounds, angles_ptr,
+                                nclasses, ws_ptr, ws_bytes, stream)
 
 
 def hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr, ws_ptr, ws_bytes,

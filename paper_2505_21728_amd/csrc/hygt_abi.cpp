@@ -82,6 +82,28 @@ int dense_impl(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
     return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 
+int backward_impl(const float* y, const float* gy, float* gx, float* gangles, int64_t nblocks,
+                  int log2n, int rounds, const float* angles, int nclasses, void* ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    if (!sizes_ok(nblocks, log2n, rounds, nclasses)) return HYGT_EINVAL;
+    if (log2n > HYGT_BACKWARD_MAX_LOG2N) return HYGT_EINVAL;
+    const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
+    if (int s = check_workspace(ws, ws_bytes, l)) return s;
+    if (angles == nullptr || gangles == nullptr) return HYGT_EINVAL;
+    if (!aligned(angles, 4) || !aligned(gangles, 4)) return HYGT_EINVAL;
+    if (nblocks > 0) {
+        if (y == nullptr || gy == nullptr || gx == nullptr) return HYGT_EINVAL;
+        const uintptr_t align = log2n == 1 ? 8 : 16;
+        if (!aligned(y, align) || !aligned(gy, align) || !aligned(gx, align)) return HYGT_EINVAL;
+        // gx may alias gy (in place); y must be separate from both
+        if (!overlap_ok(gy, gx, nblocks, log2n)) return HYGT_EINVAL;
+        if (!overlap_ok(y, gx, nblocks, log2n) || y == gx) return HYGT_EINVAL;
+    }
+    const hipError_t e = hygt::launch_backward(y, gy, gx, gangles, nblocks, log2n, rounds,
+                                               angles, nclasses, l, hygt::ws_ptrs(ws, l), stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
 int plan_and_apply(const float* x, float* y, const int32_t* cls, int64_t nblocks, int log2n,
                    int rounds, const float* angles, int nclasses, int direction, void* ws,
                    size_t ws_bytes, hipStream_t stream) {
@@ -133,6 +155,13 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks, 
                  size_t workspace_bytes, hipStream_t stream) {
     return plan_and_apply(x, y, cls, nblocks, log2n, rounds, angles, nclasses, HYGT_INVERSE,
                           workspace, workspace_bytes, stream);
+}
+
+int hygt_backward(const float* y, const float* gy, float* gx, float* gangles, int64_t nblocks,
+                  int log2n, int rounds, const float* angles, int nclasses, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+    return backward_impl(y, gy, gx, gangles, nblocks, log2n, rounds, angles, nclasses, workspace,
+                         workspace_bytes, stream);
 }
 
 int hygt_dense_apply(const float* x, float* y, int64_t nblocks, int log2n, int rounds,

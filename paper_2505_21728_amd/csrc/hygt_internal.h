@@ -45,6 +45,7 @@ struct WsLayout {
     size_t modes = 0;        // int32 [2][C] 1 = some output needs a final sign flip
     size_t coef = 0;         // float [2][C][P][N] per-pass multipliers (two per pair)
     size_t signs = 0;        // float [2][C][N] final sign (+1 / -1) of each output
+    size_t trig = 0;         // float [C][R*d][N] (cos, sin) per pair, forward order (backward)
     size_t total = 0;
     int64_t nchunks = 0;
     int64_t chunk = 0;       // blocks per chunk (a multiple of 256)
@@ -84,6 +85,7 @@ inline WsLayout ws_layout(int64_t nblocks, int log2n, int rounds, int nclasses) 
     l.modes = take(2 * C * 4);
     l.coef = take(2 * C * static_cast<size_t>(l.passes) * l.n * 4);
     l.signs = take(2 * C * static_cast<size_t>(l.n) * 4);
+    l.trig = take(C * static_cast<size_t>(l.passes) * l.n * 4);
     l.total = off;
     return l;
 }
@@ -98,6 +100,7 @@ struct WsPtrs {
     int32_t* modes;
     float* coef;
     float* signs;
+    float* trig;
 };
 
 inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
@@ -111,10 +114,11 @@ inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
     p.modes = reinterpret_cast<int32_t*>(b + l.modes);
     p.coef = reinterpret_cast<float*>(b + l.coef);
     p.signs = reinterpret_cast<float*>(b + l.signs);
+    p.trig = reinterpret_cast<float*>(b + l.trig);
     return p;
 }
 
-// Kernel launchers (hygt_plan.hip, hygt_rotate.hip, hygt_dense.hip). Each returns the
+// Kernel launchers (hygt_plan.hip, hygt_rotate.hip, hygt_backward.hip, hygt_dense.hip). Each returns the
 // hipError_t of its launches.
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
                        const float* angles, int nclasses, const WsLayout& l,
@@ -123,6 +127,11 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
 hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                          int nclasses, int direction, const WsLayout& l, const WsPtrs& p,
                          hipStream_t stream);
+
+// Reverse-mode derivative of the forward transform (hygt_backward.hip), N <= 64.
+hipError_t launch_backward(const float* y, const float* gy, float* gx, float* gangles,
+                           int64_t nblocks, int log2n, int rounds, const float* angles,
+                           int nclasses, const WsLayout& l, const WsPtrs& p, hipStream_t stream);
 
 // Dense per-class transform (hygt_dense.hip), N = 64.
 hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,

@@ -41,48 +41,12 @@
 // an explicit fmaf or an exact sign flip, so every block of a class sees the
 // same rounding whatever the batch, tile or launch.
 
-#include "hygt_internal.h"
+#include "hygt_tile.h"
 
 namespace hygt {
 namespace {
 
-// Wavefronts (tiles) per workgroup of the rotation kernels.
-constexpr int kWaves = 4;
-// Accelerator complex dies (XCDs) that workgroups are dispatched over.
-constexpr int kXcds = 8;
-// Register budget of the rotation kernels: resident wavefronts per SIMD
-// (N <= 64; a lane holding 128 values needs about 160 registers, three
-// wavefronts per SIMD).
-#ifndef HYGT_WAVES_PER_SIMD
-#define HYGT_WAVES_PER_SIMD 5
-#endif
-constexpr int kWavesPerSimd = HYGT_WAVES_PER_SIMD;
-constexpr int kWavesPerSimdWide = 3;
-
-template <int I, int End>
-struct StaticFor {
-    template <typename F>
-    __device__ __forceinline__ static void run(F&& f) {
-        if constexpr (I < End) {
-            f(std::integral_constant<int, I>{});
-            StaticFor<I + 1, End>::run(f);
-        }
-    }
-};
-
-constexpr int ins0(int j, int k) { return ((j >> k) << (k + 1)) | (j & ((1 << k) - 1)); }
-
-// XOR swizzle of a block's 16-byte chunk index inside a tile's LDS image.
-// With chunk q of block b at slot b*CH + (q ^ swz(b)), 8 (and 16) consecutive
-// lanes reading the same q touch 8 (16) distinct 16-byte bank groups.
-template <int CH>
-__device__ __forceinline__ int swz(int b) {
-    if constexpr (CH == 16) return b & 15;
-    else if constexpr (CH == 8) return (b ^ (b >> 3)) & 7;
-    else if constexpr (CH == 4) return ((b >> 1) ^ (b >> 3)) & 3;
-    else if constexpr (CH == 2) return ((b >> 2) ^ (b >> 3)) & 1;
-    else return 0;
-}
+using namespace tile;
 
 // The passes act on T blocks at once (one per tile of the wavefront, all of
 // one class): every multiplier fetched is used by T blocks.
@@ -202,113 +166,6 @@ __device__ __forceinline__ void run_passes_split(float (&v)[1][128], const float
             v[0][i] *= sign[h * (N / 2) + i];
         });
     }
-}
-
-__device__ __forceinline__ int valid_block(int b, int64_t nblocks) {
-    return (b >= 0 && b < nblocks) ? b : -1;  // never touch memory outside x / y
-}
-
-// A tile goes out from registers through LDS in PARTS parts of CHP 16-byte chunks per
-// block (CHP = min(N/4, kChunksPerPart)); a wavefront's LDS image of one part
-// is 64 * CHP * 16 bytes.
-#ifndef HYGT_CHUNKS_PER_PART
-#define HYGT_CHUNKS_PER_PART 8
-#endif
-constexpr int kChunksPerPart = HYGT_CHUNKS_PER_PART;
-template <int D>
-struct TileGeo {
-    static constexpr int N = 1 << D;
-    static constexpr bool SPLIT = D > kLaneBits;     // two wavefronts per tile
-    static constexpr int V = SPLIT ? N / 2 : N;      // values per lane
-    static constexpr int LD = SPLIT ? kLaneBits : D; // log2(V)
-    static constexpr int CH = V / 4;                 // 16-byte chunks per lane's row
-    static constexpr int CHP = CH < 1 ? 1 : CH < kChunksPerPart ? CH : kChunksPerPart;  // per part
-    static constexpr int PARTS = CH / CHP;
-    static constexpr int BPI = 64 / CHP;             // blocks per memory instruction
-    static constexpr int WAVES = SPLIT ? 2 : kWaves;  // wavefronts per workgroup
-    static constexpr int TILES = SPLIT ? 1 : kWaves;  // tiles per workgroup
-    static constexpr int OCC = D < 7 ? kWavesPerSimd : kWavesPerSimdWide;
-};
-
-// Block id handled by memory instruction i of every part: block
-// b = i*BPI + lane/CHP of the tile.
-template <int D>
-__device__ __forceinline__ void instr_blocks(int* bb, int blk, int lane) {
-    using G = TileGeo<D>;
-    StaticFor<0, G::CHP>::run([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        bb[i] = __builtin_amdgcn_ds_bpermute((i * G::BPI + lane / G::CHP) << 2, blk);
-    });
-}
-
-// Outputs are written with non-temporal stores: they are not read again by
-// this launch, and keeping them out of the caches leaves room for the inputs.
-__device__ __forceinline__ void store_nt(float* p, float4 f) {
-    typedef float vf4 __attribute__((ext_vector_type(4)));
-    const vf4 w = {f.x, f.y, f.z, f.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<vf4*>(p));
-}
-
-template <int D>
-__device__ __forceinline__ void scatter_part(float* __restrict__ y, const float4* L,
-                                             const int* bb, int lane, int part) {
-    using G = TileGeo<D>;
-    StaticFor<0, G::CHP>::run([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        const int b = i * G::BPI + lane / G::CHP;
-        const int ch = part * G::CHP + ((lane % G::CHP) ^ swz<G::CHP>(b));
-        const float4 f = L[i * 64 + lane];
-        if (bb[i] >= 0) store_nt(y + static_cast<int64_t>(bb[i]) * G::N + ch * 4, f);
-    });
-}
-
-// Brings a lane's row (its block, or for N = 256 its half of the block)
-// into registers: V / 4 loads of 16 bytes, all in flight at once, so the
-// first passes can start on the chunks that arrive first.
-template <int D>
-__device__ __forceinline__ void load_row(const float* __restrict__ x, int blk, float* v) {
-    using G = TileGeo<D>;
-    if (blk < 0) return;
-    const float4* src = reinterpret_cast<const float4*>(x + static_cast<int64_t>(blk) * G::N);
-    StaticFor<0, G::V / 4>::run([&](auto qq) {
-        constexpr int q = decltype(qq)::value;
-        const float4 f = src[q];
-        v[4 * q + 0] = f.x;
-        v[4 * q + 1] = f.y;
-        v[4 * q + 2] = f.z;
-        v[4 * q + 3] = f.w;
-    });
-}
-
-// Writes part P of a tile back: each lane writes its block's CHP chunks of
-// the part into L, then the transposed slots go out as whole blocks.
-template <int D, int P>
-__device__ __forceinline__ void store_part(float* __restrict__ y, float4* L, const int* bb,
-                                           const float* v, int lane, int sw) {
-    using G = TileGeo<D>;
-    constexpr int CHP = G::CHP;
-    StaticFor<0, CHP>::run([&](auto qq) {
-        constexpr int q = decltype(qq)::value;
-        constexpr int e = 4 * (P * CHP + q);
-        L[lane * CHP + (q ^ sw)] = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-    });
-    // LDS executes one wavefront's operations in order; only the compiler's
-    // ordering of the transposed reads after the row writes needs pinning.
-    asm volatile("" ::: "memory");
-    scatter_part<D>(y, L, bb, lane, P);
-    // Later row writes into L must not overtake the transposed reads.
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-}
-
-// Tiles of workgroup w: workgroups are dispatched round-robin over the
-// XCDs (w mod 8), so workgroup w takes the (w / 8)-th group of tiles of
-// XCD (w mod 8)'s contiguous share of the class-sorted tile list. The waves
-// that share an XCD's scalar caches then work on one or two classes at a
-// time. The grid is a multiple of 8 workgroups.
-__device__ __forceinline__ int64_t xcd_tile_group() {
-    const int64_t w = blockIdx.x;
-    const int64_t per_xcd = gridDim.x / kXcds;
-    return (w % kXcds) * per_xcd + w / kXcds;
 }
 
 // N >= 4: LDS-staged tiles, one lane per block; one tile per wavefront, or

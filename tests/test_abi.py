@@ -130,3 +130,18 @@ def test_dense_rejects():
     assert d(x, x + 256, 100, 6, 2, 3, m, FAKE, need, 0) == _abi.HYGT_EINVAL  # overlap
     assert d(x, y, 100, 6, 2, 3, m, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
     assert d(0, 0, 0, 6, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_OK              # empty no-op
+
+
+def test_backward_rejects():
+    need = _abi.hygt_workspace_bytes(100, 6, 2, 3)
+    b = _abi.hygt_backward
+    y, gy, gx, ga, ang = FAKE, FAKE * 2, FAKE * 4, FAKE * 8, FAKE * 16
+    need7 = _abi.hygt_workspace_bytes(100, 7, 2, 3)
+    assert b(y, gy, gx, ga, 100, 7, 2, ang, 3, FAKE, need7, 0) == _abi.HYGT_EINVAL     # N > 64
+    assert b(y, gy, gx, 0, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL      # gangles NULL
+    assert b(y, gy, gx, ga, 100, 6, 2, 0, 3, FAKE, need, 0) == _abi.HYGT_EINVAL       # angles NULL
+    assert b(0, gy, gx, ga, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL     # y NULL
+    assert b(y, gy, y, ga, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL      # gx == y
+    assert b(y, gy, gy + 16, ga, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL  # overlap
+    assert b(y + 4, gy, gx, ga, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL   # misaligned
+    assert b(y, gy, gx, ga, 100, 6, 2, ang, 3, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE

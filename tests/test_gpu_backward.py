@@ -1,0 +1,176 @@
+"""GPU parity of the backward (angle and input gradients) against the FP64
+oracle, through the C ABI and through torch.autograd.
+
+Both sides get the same inputs: y from the GPU forward (FP32), gy = dL/dy of
+the class log-variance loss computed by the oracle from that y and rounded to
+FP32. Tolerances: dL/dx as the forward (relative L2 <= 1e-5 per block);
+dL/dangles, a sum over each class's blocks of FP32 terms (relative L2 over
+each class's angles <= 1e-4, see test docstrings).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hygt_oracle as orc
+from paper_2505_21728_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-5
+TOL_A = 1e-5
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _to(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rel(a, b):
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / den if den > 0 else np.linalg.norm(a)
+
+
+def _check_grads(gx, ga, gx_ref, ga_ref, cls, nclasses, what):
+    eb = orc.rel_l2_per_block(gx, gx_ref)
+    assert eb.max() <= TOL_X, f"{what}: dL/dx per-block {eb.max():.3e}"
+    ea = _rel(ga, ga_ref)
+    per_class = [_rel(ga[c], ga_ref[c]) for c in range(nclasses) if np.any(cls == c)]
+    _say(f"[gpu] {what}: dL/dx {eb.max():.2e}, dL/dangles global {ea:.2e}, "
+         f"worst class {max(per_class):.2e}")
+    assert ea <= TOL_A and max(per_class) <= TOL_A, f"{what}: dL/dangles {ea:.3e}"
+    for c in range(nclasses):
+        if not np.any(cls == c):
+            assert np.all(ga[c] == 0), f"{what}: empty class {c} has a gradient"
+
+
+def _run(x, cls, ang, dev):
+    import paper_2505_21728_amd as hygt
+    at = _to(ang, dev)
+    plan = hygt.Plan(at, _to(cls, dev))
+    y = plan.forward(_to(x, dev))
+    y64 = y.cpu().numpy().astype(np.float64)
+    gy = orc.class_log_variance_grad(y64, cls, ang.shape[0]).astype(np.float32)
+    gx, ga = plan.backward(y, _to(gy, dev), at)
+    torch.cuda.synchronize()
+    gx_ref, ga_ref = orc.backward(y64, gy.astype(np.float64), cls, ang)
+    return gx.cpu().numpy().astype(np.float64), ga.cpu().numpy().astype(np.float64), gx_ref, ga_ref
+
+
+def test_backward_config4_small():
+    """8x8 AR(1) blocks, 35 classes, R = 4, 8191 blocks (ragged tiles).
+
+    dL/dangles: each term g_m y_n - g_n y_m carries a few FP32 rounding errors
+    relative to |g||y|, recomputed inputs add a few ulps per pass walked
+    back, and each class sums ~234 such terms of both signs; measured errors
+    are 1e-7 here and at most 2.2e-6 over the size sweep, the bound is 1e-5."""
+    dev = _dev()
+    ang = synth.angles(35, 4, 6)
+    x = synth.ar1_blocks(8191, 8, seed=31)
+    cls = synth.classes(8191, 35, seed=32)
+    _check_grads(*_run(x, cls, ang, dev), cls, 35, "backward cfg4-small")
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("rounds", [1, 3])
+def test_backward_sizes(d, rounds):
+    dev = _dev()
+    rng = np.random.default_rng(200 + 10 * d + rounds)
+    nb, C = 300, 4
+    ang = rng.uniform(-math.pi, math.pi, (C, rounds, d, 1 << (d - 1))).astype(np.float32)
+    x = (20 * rng.standard_normal((nb, 1 << d))).astype(np.float32)
+    cls = rng.integers(0, C - 1, nb).astype(np.int32)      # class C-1 stays empty
+    _check_grads(*_run(x, cls, ang, dev), cls, C, f"backward d={d} R={rounds}")
+
+
+def test_backward_fd_256_blocks():
+    """The gradient step's check: 256 8x8 AR(1) blocks, 35 classes, R = 4;
+    the GPU angle gradient against central differences of the FP64 loss at
+    40 sampled angles."""
+    dev = _dev()
+    ang = synth.angles(35, 4, 6)
+    x = synth.ar1_blocks(256, 8, seed=5)
+    cls = synth.classes(256, 35, seed=6)
+    _, ga, _, _ = _run(x, cls, ang, dev)
+    a64, x64 = ang.astype(np.float64), x.astype(np.float64)
+
+    def loss(a):
+        return orc.class_log_variance_loss(orc.forward(x64, cls, a), cls, 35)
+
+    rng = np.random.default_rng(3)
+    present = np.unique(cls)
+    scale = np.abs(ga).max()
+    worst = 0.0
+    for _ in range(40):
+        idx = (int(rng.choice(present)), int(rng.integers(4)), int(rng.integers(6)),
+               int(rng.integers(32)))
+        a1, a2 = a64.copy(), a64.copy()
+        a1[idx] += 1e-5
+        a2[idx] -= 1e-5
+        fd = (loss(a1) - loss(a2)) / 2e-5
+        worst = max(worst, abs(fd - ga[idx]) / scale)
+    _say(f"[gpu] backward vs FD on 256 blocks: worst {worst:.2e} of the largest component")
+    assert worst <= 1e-5
+
+
+def test_autograd_function_matches_oracle():
+    """y = hygt.transform(x, angles, cls); the class log-variance loss written
+    with torch operations; loss.backward() gives dL/dx and dL/dangles through
+    the HIP backward."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    C, nb = 35, 4000
+    ang = synth.angles(C, 4, 6)
+    x = synth.ar1_blocks(nb, 8, seed=41)
+    cls = synth.classes(nb, C, seed=42)
+    xt = _to(x, dev).requires_grad_(True)
+    at = _to(ang, dev).requires_grad_(True)
+    ct = _to(cls, dev)
+    y = hygt.transform(xt, at, ct)
+    counts = torch.zeros(C, device=dev).index_add_(0, ct.long(), torch.ones(nb, device=dev))
+    sums = torch.zeros(C, 64, device=dev).index_add_(0, ct.long(), y * y)
+    present = counts > 0
+    var = sums[present] / counts[present, None]
+    loss = torch.log(var + 1e-6).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    y64 = y.detach().cpu().numpy().astype(np.float64)
+    gy = orc.class_log_variance_grad(y64, cls, C)
+    gx_ref, ga_ref = orc.backward(y64, gy, cls, ang)
+    gx = xt.grad.cpu().numpy().astype(np.float64)
+    ga = at.grad.cpu().numpy().astype(np.float64)
+    # torch's loss gradient is FP32 (one more rounding of gy than the oracle's)
+    assert _rel(gx, gx_ref) <= 1e-4
+    assert _rel(ga, ga_ref) <= 1e-4
+    assert float(loss) == pytest.approx(orc.class_log_variance_loss(y64, cls, C), rel=1e-5)
+
+
+def test_backward_zero_gradient_and_in_place():
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    ang = synth.angles(3, 2, 4)
+    x = synth.gaussian_blocks(200, 16, seed=7)
+    cls = (np.arange(200) % 3).astype(np.int32)
+    at = _to(ang, dev)
+    plan = hygt.Plan(at, _to(cls, dev))
+    y = plan.forward(_to(x, dev))
+    gx, ga = plan.backward(y, torch.zeros_like(y), at)
+    assert torch.count_nonzero(gx) == 0 and torch.count_nonzero(ga) == 0
+    gy = _to(np.random.default_rng(9).standard_normal((200, 16)).astype(np.float32), dev)
+    gx_out, ga_out = plan.backward(y, gy, at)
+    gy_in = gy.clone()
+    gx_in, _ = plan.backward(y, gy_in, at, gx=gy_in)
+    assert torch.equal(gx_in, gx_out)
