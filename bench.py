@@ -40,7 +40,7 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak, GB/s
 # used only while the kernel sources still hash to the recorded value.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rotate_kernel_n64_2p20_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_21728_amd", "csrc", f)
-                  for f in ("hygt_rotate.hip", "hygt_internal.h")]
+                  for f in ("hygt_rotate.hip", "hygt_tile.h", "hygt_internal.h")]
 NBLOCKS = 1 << 20
 RING = 4                      # distinct input batches cycled by the timed steps
 LOG2N = 6
@@ -143,6 +143,41 @@ def _klt_comparison(torch, hygt, at, cs, xs, steps):
             "hygt_angle_bytes_f32": C * ROUNDS * LOG2N * (N // 2) * 4}
 
 
+def _grad_step(torch, hygt, at, cs, xs, steps):
+    """The gradient step of the training configuration (same 2^20 8x8 blocks,
+    35 classes, R = 4): the backward of the forward transform, from y and
+    dL/dy of the class log-variance loss, giving dL/dx and dL/dangles."""
+    dev = xs[0].device
+    plans = [hygt.Plan(at, c) for c in cs]
+    ys, gys = [], []
+    for k, p in enumerate(plans):
+        y = p.forward(xs[k])
+        ct = cs[k].long()
+        counts = torch.zeros(NCLASSES, device=dev).index_add_(
+            0, ct, torch.ones(NBLOCKS, device=dev))
+        var = torch.zeros(NCLASSES, N, device=dev).index_add_(0, ct, y * y) / counts[:, None]
+        gys.append((2.0 * y / (counts[ct, None] * (var[ct] + 1e-6))).contiguous())
+        ys.append(y)
+    gx = torch.empty_like(xs[0])
+    ga = torch.empty_like(at)
+    for k in range(2):
+        plans[k % RING].backward(ys[k % RING], gys[k % RING], at, gx=gx, gangles=ga)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        ev[2 * i].record(stream)
+        plans[i % RING].backward(ys[i % RING], gys[i % RING], at, gx=gx, gangles=ga)
+        ev[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)) / steps
+    launch_bytes = NBLOCKS * (3 * 4 * N + 4)   # read y and dL/dy, write dL/dx, block ids
+    return {"kernel": "backward_prep_kernel + backward_kernel<6>", "ms": ms,
+            "gbps": launch_bytes / (ms / 1e3) / 1e9,
+            "bytes_per_call": launch_bytes,
+            "flops_per_call": NBLOCKS * ROUNDS * LOG2N * (N // 2) * 14}
+
+
 def _cpu_baseline(x, cls, ang, sample):
     from oracle import hygt_oracle as orc
 
@@ -229,6 +264,7 @@ def main():
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
     klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
+    grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -262,6 +298,7 @@ def main():
                      "bytes_per_launch": launch_bytes,
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
         "klt_dense": klt,
+        "grad_step": grad,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
