@@ -178,6 +178,64 @@ int hygt_dense_apply(const float* x, float* y, int64_t nblocks, int log2n, int r
                      int nclasses, const uint16_t* mats,
                      const void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ---- Mixed batches: several block sizes in one launch -------------------
+ *
+ * A codec transforms blocks of several sizes at once (Sec. VI uses 4x4 and
+ * 8x8 transforms side by side). A mixed batch is a list of segments, one per
+ * block size, each with its own blocks, classes and angle set; one
+ * persistent launch transforms the tiles of all segments. */
+
+#define HYGT_MAX_SEGMENTS 4
+
+typedef struct hygt_segment {
+    const float* x;       /* [nblocks][N] input, device memory */
+    float* y;             /* [nblocks][N] output; may be x, must not overlap another segment */
+    const int32_t* cls;   /* [nblocks] classes in [0, nclasses); NULL when nclasses == 1 */
+    const float* angles;  /* [nclasses][rounds][log2n][N/2] */
+    int64_t nblocks;
+    int log2n;            /* 2 .. 8 (N = 4 .. 256) */
+    int rounds;
+    int nclasses;
+    int reserved;         /* 0 */
+} hygt_segment;
+
+/* Workspace bytes for a mixed batch (0 if a segment is invalid). */
+size_t hygt_mixed_workspace_bytes(const hygt_segment* segs, int nseg);
+
+/* hygt_plan() of every segment, into consecutive parts of one workspace. */
+int hygt_mixed_plan(const hygt_segment* segs, int nseg, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/* Number of launch configurations of hygt_mixed_apply(). */
+int hygt_mixed_num_configs(void);
+
+/* One launch of the mixed kernel over all segments, forward or inverse.
+ * `config` in [0, hygt_mixed_num_configs()) picks the launch shape (grid size
+ * and whether rounds are unrolled); hygt_mixed_autotune() finds the fastest.
+ * The segments must be those of the hygt_mixed_plan() call that filled the
+ * workspace. */
+int hygt_mixed_apply(const hygt_segment* segs, int nseg, int direction, int config,
+                     const void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Times every configuration of hygt_mixed_apply() on these segments (each
+ * run once to warm up, then three times) and returns the fastest in
+ * *best_config and its mean time in microseconds in *best_us. Synchronises
+ * `stream`; writes the segments' outputs. */
+int hygt_mixed_autotune(const hygt_segment* segs, int nseg, int direction,
+                        const void* workspace, size_t workspace_bytes, hipStream_t stream,
+                        int* best_config, float* best_us);
+
+/* A captured HIP graph of hygt_mixed_plan() + hygt_mixed_apply() for fixed
+ * buffers: replaying it re-plans and transforms whatever the buffers hold.
+ * Created by stream capture on `capture_stream` (not the null stream); the
+ * handle is a host object owned by the caller. */
+typedef struct hygt_graph_s* hygt_graph;
+int hygt_mixed_graph_create(const hygt_segment* segs, int nseg, int direction, int config,
+                            void* workspace, size_t workspace_bytes, hipStream_t capture_stream,
+                            hygt_graph* graph);
+int hygt_graph_launch(hygt_graph graph, hipStream_t stream);
+int hygt_graph_destroy(hygt_graph graph);
+
 /* Waits for `stream`, then reports whether the last non-empty plan on this
  * workspace met a class index outside [0, nclasses) (HYGT_ECLASS), a HIP
  * error (HYGT_EHIP), or neither (HYGT_OK). Reads at most workspace_bytes

@@ -20,8 +20,8 @@ from ._abi import (HYGT_BACKWARD_MAX_LOG2N, HYGT_DENSE_LOG2N, HYGT_FORWARD, HYGT
                    HYGT_MAX_BLOCKS, HYGT_MAX_CLASSES, HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS,
                    HygtError)
 
-__all__ = ["Plan", "forward", "inverse", "transform", "workspace_bytes", "HygtError",
-           "HYGT_FORWARD", "HYGT_INVERSE"]
+__all__ = ["Plan", "MixedBatch", "forward", "inverse", "transform", "workspace_bytes",
+           "HygtError", "HYGT_FORWARD", "HYGT_INVERSE"]
 
 
 def _torch():
@@ -248,3 +248,139 @@ def transform(x, angles, cls):
     if _FN is None:
         _FN = _function_class()
     return _FN.apply(x, angles, cls)
+
+
+class MixedBatch:
+    """Blocks of several sizes transformed by one launch.
+
+    `segments` is a list of (x, cls, angles) or (x, y, cls, angles) tuples of
+    GPU tensors, one per block size: x and y [B, N] float32 (y defaults to a
+    new tensor; it may be x), cls [B] int32 (or None with one class), angles
+    [C, R, log2N, N/2] float32. The buffers are fixed for the object's life:
+    plan(), apply() and graph replays read and write them in place.
+    """
+
+    def __init__(self, segments, stream=None):
+        torch = _torch()
+        _require(1 <= len(segments) <= _abi.HYGT_MAX_SEGMENTS,
+                 f"1 to {_abi.HYGT_MAX_SEGMENTS} segments")
+        self.x, self.y, self.cls, self.angles, items = [], [], [], [], []
+        for seg in segments:
+            if len(seg) == 3:
+                x, cls, ang = seg
+                y = None
+            else:
+                x, y, cls, ang = seg
+            _require(isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and
+                     x.dim() == 2 and x.is_contiguous(), "x must be a contiguous [B, N] float32")
+            if y is None:
+                y = torch.empty_like(x)
+            _require(y.shape == x.shape and y.dtype == x.dtype and y.is_contiguous() and
+                     y.device == x.device, "y must match x")
+            _require(ang.is_cuda and ang.dtype == torch.float32 and ang.dim() == 4 and
+                     ang.is_contiguous(), "angles must be contiguous [C, R, d, N/2] float32")
+            nclasses, rounds, log2n, half = (int(v) for v in ang.shape)
+            _require(x.shape[1] == 1 << log2n and half == x.shape[1] // 2 and log2n >= 2,
+                     "x width must be N = 2^log2n >= 4 matching angles")
+            if cls is not None:
+                _require(cls.is_cuda and cls.dtype == torch.int32 and cls.is_contiguous() and
+                         cls.shape == (x.shape[0],), "cls must be a contiguous [B] int32")
+            self.x.append(x)
+            self.y.append(y)
+            self.cls.append(cls)
+            self.angles.append(ang)
+            items.append((x.data_ptr(), y.data_ptr(), 0 if cls is None else cls.data_ptr(),
+                          ang.data_ptr(), x.shape[0], log2n, rounds, nclasses))
+        self.device = self.x[0].device
+        self._segs = _abi.segments(items)
+        self._n = len(items)
+        self.ws_bytes = _abi.hygt_mixed_workspace_bytes(self._segs, self._n)
+        _require(self.ws_bytes > 0, "invalid segment sizes")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self._stream = stream
+        self.config = 0
+        self.plan()
+
+    def _s(self, stream):
+        return _stream_handle(stream if stream is not None else self._stream)
+
+    def plan(self, stream=None):
+        """Plans every segment (classes and angles as the buffers hold them now)."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_mixed_plan(self._segs, self._n, self.workspace.data_ptr(),
+                                      self.ws_bytes, self._s(stream))
+        _abi._check(st, "hygt_mixed_plan")
+
+    def apply(self, direction=HYGT_FORWARD, config=None, stream=None):
+        """One launch over all segments; returns the output tensors."""
+        torch = _torch()
+        cfg = self.config if config is None else config
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_mixed_apply(self._segs, self._n, direction, cfg,
+                                       self.workspace.data_ptr(), self.ws_bytes, self._s(stream))
+        _abi._check(st, "hygt_mixed_apply")
+        return self.y
+
+    def autotune(self, direction=HYGT_FORWARD, stream=None):
+        """Times every launch configuration, keeps the fastest; returns (config, us)."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st, cfg, us = _abi.hygt_mixed_autotune(self._segs, self._n, direction,
+                                                   self.workspace.data_ptr(), self.ws_bytes,
+                                                   self._s(stream))
+        _abi._check(st, "hygt_mixed_autotune")
+        self.config = cfg
+        return cfg, us
+
+    def graph(self, direction=HYGT_FORWARD, config=None, capture_stream=None):
+        """A replayable HIP graph of plan + apply for these buffers."""
+        torch = _torch()
+        cs = capture_stream if capture_stream is not None else torch.cuda.Stream(self.device)
+        cfg = self.config if config is None else config
+        with torch.cuda.device(self.device):
+            st, handle = _abi.hygt_mixed_graph_create(self._segs, self._n, direction, cfg,
+                                                      self.workspace.data_ptr(), self.ws_bytes,
+                                                      int(cs.cuda_stream))
+        _abi._check(st, "hygt_mixed_graph_create")
+        return MixedGraph(handle, self.device)
+
+    def check(self):
+        """Synchronises; raises HygtError if a segment had an out-of-range class."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize()
+        # each segment's flags sit in its part of the workspace (offsets as in
+        # hygt_mixed_workspace_bytes): re-read them through the ABI per part
+        off = 0
+        for x, ang in zip(self.x, self.angles):
+            c, r, d, _ = (int(v) for v in ang.shape)
+            part = workspace_bytes(x.shape[0], d, r, c)
+            st = _abi.hygt_check_error(self.workspace.data_ptr() + off, part, 0)
+            _abi._check(st, "hygt_check_error")
+            off += (part + 255) // 256 * 256
+
+
+class MixedGraph:
+    """A captured plan + apply of a MixedBatch; launch() replays it."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+
+    def launch(self, stream=None):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_graph_launch(self._h, _stream_handle(stream))
+        _abi._check(st, "hygt_graph_launch")
+
+    def close(self):
+        if self._h:
+            _abi._check(_abi.hygt_graph_destroy(self._h), "hygt_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

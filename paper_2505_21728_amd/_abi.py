@@ -30,8 +30,21 @@ HYGT_MAX_BLOCKS = 2147483647
 HYGT_DENSE_LOG2N = 6
 HYGT_BACKWARD_MAX_LOG2N = 6
 
-# Every exported symbol with its (restype, argtypes).
+HYGT_MAX_SEGMENTS = 4
+
 _c = ctypes
+
+
+class Segment(ctypes.Structure):
+    """struct hygt_segment of include/hygt.h."""
+    _fields_ = [("x", _c.c_void_p), ("y", _c.c_void_p), ("cls", _c.c_void_p),
+                ("angles", _c.c_void_p), ("nblocks", _c.c_int64), ("log2n", _c.c_int),
+                ("rounds", _c.c_int), ("nclasses", _c.c_int), ("reserved", _c.c_int)]
+
+
+_SEGS = _c.POINTER(Segment)
+
+# Every exported symbol with its (restype, argtypes).
 _SIGNATURES = {
     "hygt_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int, _c.c_int, _c.c_int]),
     "hygt_plan": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int, _c.c_void_p,
@@ -50,6 +63,18 @@ _SIGNATURES = {
     "hygt_dense_apply": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
                                     _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_size_t,
                                     _c.c_void_p]),
+    "hygt_mixed_workspace_bytes": (_c.c_size_t, [_SEGS, _c.c_int]),
+    "hygt_mixed_plan": (_c.c_int, [_SEGS, _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_mixed_num_configs": (_c.c_int, []),
+    "hygt_mixed_apply": (_c.c_int, [_SEGS, _c.c_int, _c.c_int, _c.c_int, _c.c_void_p,
+                                    _c.c_size_t, _c.c_void_p]),
+    "hygt_mixed_autotune": (_c.c_int, [_SEGS, _c.c_int, _c.c_int, _c.c_void_p, _c.c_size_t,
+                                       _c.c_void_p, _c.POINTER(_c.c_int),
+                                       _c.POINTER(_c.c_float)]),
+    "hygt_mixed_graph_create": (_c.c_int, [_SEGS, _c.c_int, _c.c_int, _c.c_int, _c.c_void_p,
+                                           _c.c_size_t, _c.c_void_p, _c.POINTER(_c.c_void_p)]),
+    "hygt_graph_launch": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "hygt_graph_destroy": (_c.c_int, [_c.c_void_p]),
     "hygt_check_error": (_c.c_int, [_c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_strerror": (_c.c_char_p, [_c.c_int]),
 }
@@ -138,6 +163,54 @@ def hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr, w
                      stream) -> int:
     return load().hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr,
                                    ws_ptr, ws_bytes, stream)
+
+
+def segments(items) -> "ctypes.Array[Segment]":
+    """A ctypes array of hygt_segment from (x, y, cls, angles, nblocks, log2n,
+    rounds, nclasses) tuples of integers (pointers as ints)."""
+    arr = (Segment * len(items))()
+    for i, (x, y, cls, ang, nb, d, r, c) in enumerate(items):
+        arr[i] = Segment(x, y, cls, ang, nb, d, r, c, 0)
+    return arr
+
+
+def hygt_mixed_workspace_bytes(segs, nseg) -> int:
+    return int(load().hygt_mixed_workspace_bytes(segs, nseg))
+
+
+def hygt_mixed_plan(segs, nseg, ws_ptr, ws_bytes, stream) -> int:
+    return load().hygt_mixed_plan(segs, nseg, ws_ptr, ws_bytes, stream)
+
+
+def hygt_mixed_num_configs() -> int:
+    return load().hygt_mixed_num_configs()
+
+
+def hygt_mixed_apply(segs, nseg, direction, config, ws_ptr, ws_bytes, stream) -> int:
+    return load().hygt_mixed_apply(segs, nseg, direction, config, ws_ptr, ws_bytes, stream)
+
+
+def hygt_mixed_autotune(segs, nseg, direction, ws_ptr, ws_bytes, stream):
+    best = _c.c_int(-1)
+    us = _c.c_float(0.0)
+    st = load().hygt_mixed_autotune(segs, nseg, direction, ws_ptr, ws_bytes, stream,
+                                    _c.byref(best), _c.byref(us))
+    return st, best.value, us.value
+
+
+def hygt_mixed_graph_create(segs, nseg, direction, config, ws_ptr, ws_bytes, stream):
+    handle = _c.c_void_p(None)
+    st = load().hygt_mixed_graph_create(segs, nseg, direction, config, ws_ptr, ws_bytes, stream,
+                                        _c.byref(handle))
+    return st, handle.value
+
+
+def hygt_graph_launch(handle, stream) -> int:
+    return load().hygt_graph_launch(handle, stream)
+
+
+def hygt_graph_destroy(handle) -> int:
+    return load().hygt_graph_destroy(handle)
 
 
 def hygt_check_error(ws_ptr, ws_bytes, stream) -> int:

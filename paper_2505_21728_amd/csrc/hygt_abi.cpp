@@ -5,6 +5,7 @@
 #include "hygt.h"
 
 #include <cstdint>
+#include <new>
 #include <vector>
 
 #include "hygt_internal.h"
@@ -121,7 +122,104 @@ int plan_and_apply(const float* x, float* y, const int32_t* cls, int64_t nblocks
     return apply_impl(x, y, nblocks, log2n, rounds, nclasses, direction, ws, ws_bytes, stream);
 }
 
+// ---- mixed batches ------------------------------------------------------
+
+bool segment_ok(const hygt_segment& g) {
+    return sizes_ok(g.nblocks, g.log2n, g.rounds, g.nclasses) && g.log2n >= 2;
+}
+
+// Offsets of the segments' parts of a mixed workspace, and its total size.
+size_t mixed_layout(const hygt_segment* segs, int nseg, size_t* offsets) {
+    size_t off = 0;
+    for (int i = 0; i < nseg; ++i) {
+        if (offsets) offsets[i] = off;
+        const WsLayout l =
+            hygt::ws_layout(segs[i].nblocks, segs[i].log2n, segs[i].rounds, segs[i].nclasses);
+        off = hygt::align_up(off + l.total, 256);
+    }
+    return off;
+}
+
+int check_segments(const hygt_segment* segs, int nseg) {
+    if (segs == nullptr || nseg < 1 || nseg > HYGT_MAX_SEGMENTS) return HYGT_EINVAL;
+    for (int i = 0; i < nseg; ++i)
+        if (!segment_ok(segs[i])) return HYGT_EINVAL;
+    return HYGT_OK;
+}
+
+int mixed_args(const hygt_segment* segs, int nseg, const void* ws, size_t ws_bytes,
+               hygt::MixedArgs* a) {
+    if (int s = check_segments(segs, nseg)) return s;
+    size_t offsets[HYGT_MAX_SEGMENTS];
+    const size_t total = mixed_layout(segs, nseg, offsets);
+    if (ws == nullptr || ws_bytes < total || !aligned(ws, 256)) return HYGT_EWORKSPACE;
+    *a = hygt::MixedArgs{};
+    int64_t item = 0;
+    for (int i = 0; i < nseg; ++i) {
+        const hygt_segment& g = segs[i];
+        if (g.nblocks > 0) {
+            if (g.x == nullptr || g.y == nullptr) return HYGT_EINVAL;
+            if (!aligned(g.x, 16) || !aligned(g.y, 16)) return HYGT_EINVAL;
+            if (!overlap_ok(g.x, g.y, g.nblocks, g.log2n)) return HYGT_EINVAL;
+        }
+        const WsLayout l = hygt::ws_layout(g.nblocks, g.log2n, g.rounds, g.nclasses);
+        void* part = static_cast<char*>(const_cast<void*>(ws)) + offsets[i];
+        const hygt::WsPtrs p = hygt::ws_ptrs(part, l);
+        hygt::MixedSeg& m = a->seg[i];
+        m.x = g.x;
+        m.y = g.y;
+        m.nblocks = g.nblocks;
+        m.max_tiles = g.nblocks > 0 ? l.max_tiles : 0;
+        m.tile_class = p.tile_class;
+        m.perm = p.perm;
+        m.modes = p.modes;
+        m.coef = p.coef;
+        m.signs = p.signs;
+        m.log2n = g.log2n;
+        m.rounds = g.rounds;
+        m.nclasses = g.nclasses;
+        m.item_begin = item;
+        m.items = hygt::mixed_items(g.log2n, m.max_tiles);
+        item += m.items;
+    }
+    a->nseg = nseg;
+    a->total_items = item;
+    return HYGT_OK;
+}
+
+int mixed_plan_impl(const hygt_segment* segs, int nseg, void* ws, size_t ws_bytes,
+                    hipStream_t stream) {
+    if (int s = check_segments(segs, nseg)) return s;
+    size_t offsets[HYGT_MAX_SEGMENTS];
+    const size_t total = mixed_layout(segs, nseg, offsets);
+    if (ws == nullptr || ws_bytes < total || !aligned(ws, 256)) return HYGT_EWORKSPACE;
+    for (int i = 0; i < nseg; ++i) {
+        const hygt_segment& g = segs[i];
+        const WsLayout l = hygt::ws_layout(g.nblocks, g.log2n, g.rounds, g.nclasses);
+        if (int s = plan_impl(g.cls, g.nblocks, g.log2n, g.rounds, g.angles, g.nclasses,
+                              static_cast<char*>(ws) + offsets[i], l.total, stream))
+            return s;
+    }
+    return HYGT_OK;
+}
+
+int mixed_apply_impl(const hygt_segment* segs, int nseg, int direction, int config,
+                     const void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (direction != HYGT_FORWARD && direction != HYGT_INVERSE) return HYGT_EINVAL;
+    if (config < 0 || config >= hygt::kMixedConfigs) return HYGT_EINVAL;
+    hygt::MixedArgs a;
+    if (int s = mixed_args(segs, nseg, ws, ws_bytes, &a)) return s;
+    if (a.total_items == 0) return HYGT_OK;
+    const hipError_t e = hygt::launch_mixed(a, direction, config, stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
 }  // namespace
+
+struct hygt_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -169,6 +267,122 @@ int hygt_dense_apply(const float* x, float* y, int64_t nblocks, int log2n, int r
                      size_t workspace_bytes, hipStream_t stream) {
     return dense_impl(x, y, nblocks, log2n, rounds, nclasses, mats, workspace, workspace_bytes,
                       stream);
+}
+
+size_t hygt_mixed_workspace_bytes(const hygt_segment* segs, int nseg) {
+    if (check_segments(segs, nseg)) return 0;
+    return mixed_layout(segs, nseg, nullptr);
+}
+
+int hygt_mixed_plan(const hygt_segment* segs, int nseg, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream) {
+    return mixed_plan_impl(segs, nseg, workspace, workspace_bytes, stream);
+}
+
+int hygt_mixed_num_configs(void) { return hygt::kMixedConfigs; }
+
+int hygt_mixed_apply(const hygt_segment* segs, int nseg, int direction, int config,
+                     const void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    return mixed_apply_impl(segs, nseg, direction, config, workspace, workspace_bytes, stream);
+}
+
+int hygt_mixed_autotune(const hygt_segment* segs, int nseg, int direction,
+                        const void* workspace, size_t workspace_bytes, hipStream_t stream,
+                        int* best_config, float* best_us) {
+    if (best_config == nullptr || best_us == nullptr) return HYGT_EINVAL;
+    // argument errors surface from the first apply, before any timing
+    if (int s = mixed_apply_impl(segs, nseg, direction, 0, workspace, workspace_bytes, stream))
+        return s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return HYGT_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HYGT_EHIP;
+    }
+    int status = HYGT_OK;
+    float best = -1.0f;
+    int best_k = 0;
+    constexpr int kReps = 3;
+    for (int k = 0; k < hygt::kMixedConfigs && status == HYGT_OK; ++k) {
+        status = mixed_apply_impl(segs, nseg, direction, k, workspace, workspace_bytes, stream);
+        if (status) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) { status = HYGT_EHIP; break; }
+        for (int r = 0; r < kReps && status == HYGT_OK; ++r)
+            status = mixed_apply_impl(segs, nseg, direction, k, workspace, workspace_bytes,
+                                      stream);
+        if (status) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            status = HYGT_EHIP;
+            break;
+        }
+        const float us = ms * 1000.0f / kReps;
+        if (best < 0.0f || us < best) {
+            best = us;
+            best_k = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status == HYGT_OK) {
+        *best_config = best_k;
+        *best_us = best;
+    }
+    return status;
+}
+
+int hygt_mixed_graph_create(const hygt_segment* segs, int nseg, int direction, int config,
+                            void* workspace, size_t workspace_bytes, hipStream_t capture_stream,
+                            hygt_graph* graph) {
+    if (graph == nullptr || capture_stream == nullptr) return HYGT_EINVAL;
+    *graph = nullptr;
+    if (direction != HYGT_FORWARD && direction != HYGT_INVERSE) return HYGT_EINVAL;
+    if (config < 0 || config >= hygt::kMixedConfigs) return HYGT_EINVAL;
+    hygt::MixedArgs a;
+    if (int s = mixed_args(segs, nseg, workspace, workspace_bytes, &a)) return s;
+    if (hipStreamBeginCapture(capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return HYGT_EHIP;
+    int status = mixed_plan_impl(segs, nseg, workspace, workspace_bytes, capture_stream);
+    if (status == HYGT_OK)
+        status = mixed_apply_impl(segs, nseg, direction, config, workspace, workspace_bytes,
+                                  capture_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(capture_stream, &g);
+    if (status == HYGT_OK && ec != hipSuccess) status = HYGT_EHIP;
+    if (status != HYGT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return status;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return HYGT_EHIP;
+    }
+    auto* h = new (std::nothrow) hygt_graph_s;
+    if (h == nullptr) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(g);
+        return HYGT_EHIP;
+    }
+    h->graph = g;
+    h->exec = exec;
+    *graph = h;
+    return HYGT_OK;
+}
+
+int hygt_graph_launch(hygt_graph graph, hipStream_t stream) {
+    if (graph == nullptr) return HYGT_EINVAL;
+    return hipGraphLaunch(graph->exec, stream) == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
+int hygt_graph_destroy(hygt_graph graph) {
+    if (graph == nullptr) return HYGT_OK;
+    int status = HYGT_OK;
+    if (hipGraphExecDestroy(graph->exec) != hipSuccess) status = HYGT_EHIP;
+    if (hipGraphDestroy(graph->graph) != hipSuccess) status = HYGT_EHIP;
+    delete graph;
+    return status;
 }
 
 int hygt_check_error(const void* workspace, size_t workspace_bytes, hipStream_t stream) {

@@ -24,11 +24,12 @@ constexpr int64_t kMaxChunks = 1024;
 // Threads per plan workgroup (>= N/2 for the table builders, N <= 256).
 constexpr int kPlanThreads = 256;
 // Hypercube dimensions kept inside one wavefront lane: a lane holds at most
-// 128 values, so for N = 256 two wavefronts share each tile, one per half of
-// every block, and the passes along bit 7 pair values of different
-// wavefronts. Those passes use the plain (cos, sin) form of the rotation,
-// the others the lifting form (see hygt_plan.hip).
-constexpr int kLaneBits = 7;
+// 64 values, so for N = 128 (256) two (four) wavefronts share each tile,
+// wavefront q holding values 64q .. 64q+63 of every block, and the passes
+// along bits 6 and 7 pair values of different wavefronts. Those passes use
+// the plain (cos, sin) form of the rotation, the others the lifting form
+// (see hygt_plan.hip).
+constexpr int kLaneBits = 6;
 
 // Device-side header at the start of the workspace.
 struct alignas(256) PlanHeader {
@@ -132,6 +133,37 @@ hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, i
 hipError_t launch_backward(const float* y, const float* gy, float* gx, float* gangles,
                            int64_t nblocks, int log2n, int rounds, const float* angles,
                            int nclasses, const WsLayout& l, const WsPtrs& p, hipStream_t stream);
+
+// Mixed batches: several block sizes, each a segment with its own plan,
+// transformed by one persistent launch (hygt_rotate.hip).
+constexpr int kMaxSegments = 4;
+struct MixedSeg {
+    const float* x;
+    float* y;
+    int64_t nblocks;
+    int64_t max_tiles;
+    const int32_t* tile_class;
+    const int32_t* perm;
+    const int32_t* modes;
+    const float* coef;
+    const float* signs;
+    int64_t item_begin;  // first work item of the segment in the launch
+    int64_t items;       // work items: 4 tiles (N <= 128) or 2 tiles (N = 256)
+    int log2n;
+    int rounds;
+    int nclasses;
+    int pad;
+};
+struct MixedArgs {
+    MixedSeg seg[kMaxSegments];
+    int64_t total_items;
+    int nseg;
+    int pad;
+};
+// Launch configurations of the mixed kernel (see mixed_config()).
+constexpr int kMixedConfigs = 8;
+int64_t mixed_items(int log2n, int64_t max_tiles);
+hipError_t launch_mixed(const MixedArgs& a, int direction, int config, hipStream_t stream);
 
 // Dense per-class transform (hygt_dense.hip), N = 64.
 hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,

@@ -41,6 +41,8 @@
 // an explicit fmaf or an exact sign flip, so every block of a class sees the
 // same rounding whatever the batch, tile or launch.
 
+#include <algorithm>
+
 #include "hygt_tile.h"
 
 namespace hygt {
@@ -98,18 +100,21 @@ __device__ __forceinline__ void run_passes(float (&v)[T][1 << D], const float* _
     }
 }
 
-// N = 256: a pass along bit 7 pairs value j of wavefront 0 (element j) with
-// value j of wavefront 1 (element 128 + j). The wavefronts swap their values
-// through LDS, 16 per lane at a time, and each computes its own outputs:
-// y_m = c x_m + s x_n on wavefront 0, y_n = c x_n - s x_m on wavefront 1,
-// with (c, s) = cp[2j], cp[2j + 1]. `xo` is this wavefront's exchange area
-// and `xp` the other's, each two buffers of [4][64] float4; part g uses
-// buffer g % 2, so the barrier of part g + 1 also guarantees that both
-// wavefronts have read part g before either overwrites its buffer.
-__device__ __forceinline__ void cross_pass(float (&v)[128], const float* __restrict__ cp,
+// N >= 128: a pass along bit K >= 6 pairs value i of wavefront q (element
+// 64q + i, bit K - 6 of q clear) with value i of wavefront q | 2^(K-6). The
+// two swap their values through LDS, 16 per lane at a time, and each
+// computes its own outputs: y_m = c x_m + s x_n on the lower wavefront,
+// y_n = c x_n - s x_m on the upper one, with (c, s) = cp[2i], cp[2i + 1]
+// (cp already offset to the wavefront pair's first pair). `xo` is this
+// wavefront's exchange area and `xp` the partner's, each two buffers of
+// [4][64] float4; part g uses buffer g % 2, so the barrier of part g + 1 also
+// guarantees that both wavefronts have read part g before either overwrites
+// its buffer. Every wavefront of the workgroup passes the same barriers.
+template <int V>
+__device__ __forceinline__ void cross_pass(float (&v)[V], const float* __restrict__ cp,
                                            unsigned hbit, float4* xo, const float4* xp,
                                            int lane) {
-    StaticFor<0, 8>::run([&](auto gg) {
+    StaticFor<0, V / 16>::run([&](auto gg) {
         constexpr int g = decltype(gg)::value;
         constexpr int buf = g & 1;
         StaticFor<0, 4>::run([&](auto qq) {
@@ -132,45 +137,56 @@ __device__ __forceinline__ void cross_pass(float (&v)[128], const float* __restr
             constexpr int j = 16 * g + t;
             const float c = cp[2 * j];
             const float sn = cp[2 * j + 1];
-            // -s on wavefront 1: a sign-bit flip of a wave-uniform value
+            // -s on the upper wavefront: a sign-bit flip of a wave-uniform value
             const float sg = __uint_as_float(__float_as_uint(sn) ^ hbit);
             v[j] = fmaf(sg, w[t], c * v[j]);
         });
     });
 }
 
-// N = 256, wavefront h of a tile: R rounds of 8 passes in application order.
-// Passes along bits 0..6 act on the lane's 128 values with the multipliers
-// of pairs 64h .. 64h + 63 of the pass; passes along bit 7 go through
-// cross_pass. Then the final signs of elements 128h .. 128h + 127.
-template <int DIR>
-__device__ __forceinline__ void run_passes_split(float (&v)[1][128], const float* __restrict__ tbl,
+// N >= 128, wavefront q of a tile's 2^(D-6) wavefronts: R rounds of D
+// passes in application order. Passes along bits 0..5 act on the lane's 64
+// values with the multipliers of pairs 32q .. 32q + 31 of the pass; passes
+// along bits 6, 7 go through cross_pass with the partner wavefront
+// q ^ 2^(K-6), whose pairs start at 64 * (q without bit K-6). Then the final
+// signs of elements 64q .. 64q + 63. The tile's wavefronts have consecutive
+// LDS areas of 512 float4 starting at `area0`.
+template <int D, int DIR>
+__device__ __forceinline__ void run_passes_split(float (&v)[1][64], const float* __restrict__ tbl,
                                                  const float* __restrict__ sign, int has_neg,
-                                                 int rounds, int h, float4* xo, const float4* xp,
+                                                 int rounds, int q, float4* area0,
                                                  int lane) {
-    constexpr int D = 8;
-    constexpr int N = 256;
+    constexpr int N = 1 << D;
+    constexpr int V = 64;
     for (int r = 0; r < rounds; ++r) {
         StaticFor<0, D>::run([&](auto kk) {
             constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
             const float* cp = tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N;
-            if constexpr (K >= kLaneBits)
-                cross_pass(v[0], cp, static_cast<unsigned>(h) << 31, xo, xp, lane);
-            else
-                pass_lift<kLaneBits, K, 1>(v, cp + h * (N / 2));
+            if constexpr (K >= kLaneBits) {
+                constexpr int b = K - kLaneBits;
+                const int qq = ((q >> (b + 1)) << b) | (q & ((1 << b) - 1));
+                cross_pass<V>(v[0], cp + 2 * V * qq, static_cast<unsigned>((q >> b) & 1) << 31,
+                              area0 + 512 * q, area0 + 512 * (q ^ (1 << b)), lane);
+            } else {
+                pass_lift<kLaneBits, K, 1>(v, cp + q * V);
+            }
         });
     }
     if (has_neg) {
-        StaticFor<0, N / 2>::run([&](auto ii) {
+        StaticFor<0, V>::run([&](auto ii) {
             constexpr int i = decltype(ii)::value;
-            v[0][i] *= sign[h * (N / 2) + i];
+            v[0][i] *= sign[q * V + i];
         });
     }
 }
 
-// N >= 4: LDS-staged tiles, one lane per block; one tile per wavefront, or
-// for N = 256 one tile per pair of wavefronts (a workgroup), wavefront h
-// holding half h of every block.
+// One tile of a transform of N >= 4: loads, passes, stores. For N >= 128
+// the tile belongs to 2^(D-6) wavefronts, this one (number q of them)
+// holding values 64q .. 64q+63 of every block; the tile's wavefronts have
+// consecutive LDS areas of 512 float4 from `area0`, and `L` is this
+// wavefront's own (for N <= 64, the only one). A class c < 0 marks a
+// dummy tile (N >= 128 only), which touches no memory but takes part in the
+// tile's barriers.
 //
 // x and y may be the same array (in place): every value is read by the
 // wavefront that owns it and written back only after that read has
@@ -178,47 +194,38 @@ __device__ __forceinline__ void run_passes_split(float (&v)[1][128], const float
 // (which let the per-tile class loads stay scalar) hold for every pair of
 // accesses that the compiler could reorder.
 template <int D, int DIR, int RT>
-__global__ __launch_bounds__(64 * TileGeo<D>::WAVES)
-__attribute__((amdgpu_waves_per_eu(TileGeo<D>::OCC)))
-void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t nblocks,
-                   int rounds, int nclasses, int64_t max_tiles,
-                   const int32_t* __restrict__ tile_class, const int32_t* __restrict__ perm,
-                   const int32_t* __restrict__ modes, const float* __restrict__ coef,
-                   const float* __restrict__ signs) {
+__device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* __restrict__ y,
+                                            int64_t nblocks, int rounds, int nclasses,
+                                            int64_t t0, int c, int q,
+                                            const int32_t* __restrict__ perm,
+                                            const int32_t* __restrict__ modes,
+                                            const float* __restrict__ coef,
+                                            const float* __restrict__ signs, float4* L,
+                                            float4* area0, int lane) {
     using G = TileGeo<D>;
     constexpr int N = G::N;
     constexpr int CHP = G::CHP;
     constexpr int T = G::SPLIT ? 1 : kTilesPerWave;
-    // Staging of a part; for N = 256 also the exchange area (2 x 4 x 64 float4).
-    __shared__ float4 lds[G::WAVES][kTile * CHP];
-    static_assert(!G::SPLIT || kTile * CHP >= 2 * 4 * 64, "exchange area too small");
-
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int h = G::SPLIT ? wv : 0;  // half of every block held by this wavefront
-    // This wavefront's T consecutive tiles; the plan gives them one class.
-    const int64_t t0 = G::SPLIT ? xcd_tile_group() : (xcd_tile_group() * kWaves + wv) * T;
-    if (t0 >= max_tiles) return;  // both wavefronts of a split tile leave together
-    const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
-    if (c < 0) return;  // past the last tile
-    const float* xh = x + h * G::V;
-    float* yh = y + h * G::V;
-    float4* L = lds[wv];
+    static_assert(!G::SPLIT || kTile * CHP == 512, "split tiles use areas of 512 float4");
+    const float* xh = x + q * G::V;
+    float* yh = y + q * G::V;
     int blk[T];
     float v[T][G::V];
     StaticFor<0, T>::run([&](auto uu) {
         constexpr int u = decltype(uu)::value;
-        blk[u] = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
+        // lanes without a block compute on whatever their registers hold and
+        // store nothing
+        blk[u] = c < 0 ? -1 : valid_block(perm[(t0 + u) * kTile + lane], nblocks);
         load_row<D>(xh, blk[u], v[u]);
     });
 
     const size_t passes = static_cast<size_t>(rounds) * D;
-    const size_t table = static_cast<size_t>(DIR) * nclasses + c;
+    const size_t table = static_cast<size_t>(DIR) * nclasses + (c < 0 ? 0 : c);
     if constexpr (G::SPLIT) {
-        run_passes_split<DIR>(v, coef + table * passes * N, signs + table * N, modes[table],
-                              rounds, h, lds[h], lds[1 - h], lane);
-        // The other wavefront's last reads of this wavefront's exchange area
-        // come before the stores below reuse it for staging.
+        run_passes_split<D, DIR>(v, coef + table * passes * N, signs + table * N, modes[table],
+                                 rounds, q, area0, lane);
+        // The partners' last reads of this wavefront's exchange area come
+        // before the stores below reuse it for staging.
         __syncthreads();
     } else {
         run_passes<D, DIR, RT, T>(v, coef + table * passes * N, signs + table * N,
@@ -241,6 +248,32 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
             store_part<D, decltype(pp)::value>(yh, L, bb, v[u], lane2, sw2);
         });
     });
+}
+
+// N >= 4: one tile per wavefront, or for N = 256 one tile per pair of
+// wavefronts (a workgroup), wavefront h holding half h of every block.
+template <int D, int DIR, int RT>
+__global__ __launch_bounds__(64 * TileGeo<D>::WAVES)
+__attribute__((amdgpu_waves_per_eu(TileGeo<D>::OCC)))
+void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t nblocks,
+                   int rounds, int nclasses, int64_t max_tiles,
+                   const int32_t* __restrict__ tile_class, const int32_t* __restrict__ perm,
+                   const int32_t* __restrict__ modes, const float* __restrict__ coef,
+                   const float* __restrict__ signs) {
+    using G = TileGeo<D>;
+    // Staging of a part; for N >= 128 also the exchange area (2 x 4 x 64 float4).
+    __shared__ float4 lds[G::WAVES][kTile * G::CHP];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int q = G::SPLIT ? wv : 0;  // share of every block held by this wavefront
+    // This wavefront's tiles; the plan gives them one class.
+    const int64_t t0 =
+        G::SPLIT ? xcd_tile_group() : (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    if (t0 >= max_tiles) return;  // all wavefronts of a split tile leave together
+    const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
+    if (c < 0) return;  // past the last tile
+    rotate_tile<D, DIR, RT>(x, y, nblocks, rounds, nclasses, t0, c, q, perm, modes, coef, signs,
+                            lds[wv], lds[0], lane);
 }
 
 // N == 2: one 8-byte block per lane, read and written directly.
@@ -325,6 +358,132 @@ hipError_t launch_dir(const float* x, float* y, int64_t nblocks, int log2n, int 
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Mixed batches: one persistent launch over the tiles of several block sizes
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Resident wavefronts per SIMD of the mixed kernel: the persistent loop and
+// the per-segment arguments cost some registers over the plain kernels,
+// which at five wavefronts per SIMD would spill.
+constexpr int kMixedWavesPerSimd = 4;
+// Workgroups per compute unit at that budget (four wavefronts each).
+constexpr int kMixedWgPerCu = kMixedWavesPerSimd;
+constexpr int kComputeUnits = 256;
+
+// Work item `local` of segment g: four tiles, one per wavefront (N <= 64),
+// or 4 / 2^(D-6) tiles of N >= 128, each shared by 2^(D-6) consecutive
+// wavefronts. With UNROLL, segments with N <= 64 and R in {1, 2, 4} run with
+// their rounds unrolled at compile time.
+template <int D, int DIR, bool UNROLL>
+__device__ __forceinline__ void mixed_item(const MixedSeg& g, int64_t local, int wv, int lane,
+                                           float4 (*lds)[512]) {
+    using G = TileGeo<D>;
+    if constexpr (G::SPLIT) {
+        constexpr int S = G::SHARE;
+        const int first = wv & ~(S - 1);  // first wavefront of this tile
+        const int64_t t0 = local * (4 / S) + wv / S;
+        int c = -1;  // a dummy tile still joins the workgroup's barriers
+        if (t0 < g.max_tiles) c = __builtin_amdgcn_readfirstlane(g.tile_class[t0]);
+        rotate_tile<D, DIR, 0>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, wv - first,
+                               g.perm, g.modes, g.coef, g.signs, lds[wv], lds[first], lane);
+    } else {
+        const int64_t t0 = local * 4 + wv;
+        if (t0 >= g.max_tiles) return;
+        const int c = __builtin_amdgcn_readfirstlane(g.tile_class[t0]);
+        if (c < 0) return;
+        if constexpr (UNROLL && D <= 6) {
+            switch (g.rounds) {
+                case 1:
+                    rotate_tile<D, DIR, 1>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
+                                           g.perm, g.modes, g.coef, g.signs, lds[wv], lds[wv],
+                                           lane);
+                    return;
+                case 2:
+                    rotate_tile<D, DIR, 2>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
+                                           g.perm, g.modes, g.coef, g.signs, lds[wv], lds[wv],
+                                           lane);
+                    return;
+                case 4:
+                    rotate_tile<D, DIR, 4>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
+                                           g.perm, g.modes, g.coef, g.signs, lds[wv], lds[wv],
+                                           lane);
+                    return;
+                default:
+                    break;
+            }
+        }
+        rotate_tile<D, DIR, 0>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0, g.perm,
+                               g.modes, g.coef, g.signs, lds[wv], lds[wv], lane);
+    }
+}
+
+// Workgroups take items blockIdx.x, blockIdx.x + gridDim.x, ... of the
+// concatenated item lists of the segments. Every wavefront of a workgroup
+// walks the same items, so the N = 256 pairs always meet at the same
+// barriers.
+template <int DIR, bool UNROLL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixedWavesPerSimd)))
+void mixed_kernel(MixedArgs a) {
+    __shared__ float4 lds[4][512];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t item = blockIdx.x; item < a.total_items; item += gridDim.x) {
+        // the segment, chosen with constant indices so that its fields stay
+        // kernel-argument loads
+        MixedSeg g = a.seg[0];
+        StaticFor<1, kMaxSegments>::run([&](auto ss) {
+            constexpr int k = decltype(ss)::value;
+            if (k < a.nseg && item >= a.seg[k].item_begin) g = a.seg[k];
+        });
+        const int64_t local = item - g.item_begin;
+        switch (g.log2n) {
+            case 2: mixed_item<2, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            case 3: mixed_item<3, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            case 4: mixed_item<4, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            case 5: mixed_item<5, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            case 6: mixed_item<6, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            case 7: mixed_item<7, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            case 8: mixed_item<8, DIR, UNROLL>(g, local, wv, lane, lds); break;
+            default: break;
+        }
+    }
+}
+
+// Configuration k: bit 0 = rounds unrolled; bits 1-2 = grid: one workgroup
+// per item, or 1, 2 or 4 waves of resident workgroups walking the items.
+template <int DIR>
+hipError_t launch_mixed_dir(const MixedArgs& a, int config, hipStream_t stream) {
+    const bool unroll = config & 1;
+    const int grid_mode = (config >> 1) & 3;
+    int64_t grid = a.total_items;
+    if (grid_mode > 0) {
+        const int64_t resident = static_cast<int64_t>(kComputeUnits) * kMixedWgPerCu;
+        grid = std::min<int64_t>(grid, resident << (grid_mode - 1));
+    }
+    if (grid <= 0) return hipSuccess;
+    if (unroll)
+        hipLaunchKernelGGL((mixed_kernel<DIR, true>), dim3(static_cast<unsigned>(grid)), dim3(256),
+                           0, stream, a);
+    else
+        hipLaunchKernelGGL((mixed_kernel<DIR, false>), dim3(static_cast<unsigned>(grid)),
+                           dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t mixed_items(int log2n, int64_t max_tiles) {
+    const int64_t per = log2n > kLaneBits ? 4 >> (log2n - kLaneBits) : 4;
+    return (max_tiles + per - 1) / per;
+}
+
+hipError_t launch_mixed(const MixedArgs& a, int direction, int config, hipStream_t stream) {
+    if (direction == 0) return launch_mixed_dir<0>(a, config, stream);
+    return launch_mixed_dir<1>(a, config, stream);
+}
 
 hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                          int nclasses, int direction, const WsLayout& l, const WsPtrs& p,

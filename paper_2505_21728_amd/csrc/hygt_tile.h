@@ -13,14 +13,12 @@ namespace tile {
 constexpr int kWaves = 4;
 // Accelerator complex dies (XCDs) that workgroups are dispatched over.
 constexpr int kXcds = 8;
-// Register budget of the rotation kernels: resident wavefronts per SIMD
-// (N <= 64; a lane holding 128 values needs about 160 registers, three
-// wavefronts per SIMD).
+// Register budget of the rotation kernels: resident wavefronts per SIMD (a
+// lane holds at most 64 values).
 #ifndef HYGT_WAVES_PER_SIMD
 #define HYGT_WAVES_PER_SIMD 5
 #endif
 constexpr int kWavesPerSimd = HYGT_WAVES_PER_SIMD;
-constexpr int kWavesPerSimdWide = 3;
 
 template <int I, int End>
 struct StaticFor {
@@ -61,16 +59,17 @@ constexpr int kChunksPerPart = HYGT_CHUNKS_PER_PART;
 template <int D>
 struct TileGeo {
     static constexpr int N = 1 << D;
-    static constexpr bool SPLIT = D > kLaneBits;     // two wavefronts per tile
-    static constexpr int V = SPLIT ? N / 2 : N;      // values per lane
+    static constexpr bool SPLIT = D > kLaneBits;     // several wavefronts per tile
+    static constexpr int SHARE = SPLIT ? 1 << (D - kLaneBits) : 1;  // wavefronts per tile
+    static constexpr int V = N / SHARE;              // values per lane
     static constexpr int LD = SPLIT ? kLaneBits : D; // log2(V)
     static constexpr int CH = V / 4;                 // 16-byte chunks per lane's row
     static constexpr int CHP = CH < 1 ? 1 : CH < kChunksPerPart ? CH : kChunksPerPart;  // per part
     static constexpr int PARTS = CH / CHP;
     static constexpr int BPI = 64 / CHP;             // blocks per memory instruction
-    static constexpr int WAVES = SPLIT ? 2 : kWaves;  // wavefronts per workgroup
-    static constexpr int TILES = SPLIT ? 1 : kWaves;  // tiles per workgroup
-    static constexpr int OCC = D < 7 ? kWavesPerSimd : kWavesPerSimdWide;
+    static constexpr int WAVES = SPLIT ? SHARE : kWaves;  // wavefronts per workgroup
+    static constexpr int TILES = SPLIT ? 1 : kWaves;      // tiles per workgroup
+    static constexpr int OCC = kWavesPerSimd;
 };
 
 // Block id handled by memory instruction i of every part: block

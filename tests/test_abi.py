@@ -145,3 +145,35 @@ def test_backward_rejects():
     assert b(y, gy, gy + 16, ga, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL  # overlap
     assert b(y + 4, gy, gx, ga, 100, 6, 2, ang, 3, FAKE, need, 0) == _abi.HYGT_EINVAL   # misaligned
     assert b(y, gy, gx, ga, 100, 6, 2, ang, 3, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+
+
+def _seg(nb, d, r, c, x=FAKE, y=FAKE * 64):
+    return (x, y, FAKE * 128, FAKE * 256, nb, d, r, c)
+
+
+def test_mixed_sizes_and_rejects():
+    segs = _abi.segments([_seg(100, 4, 2, 3), _seg(50, 6, 4, 35), _seg(10, 8, 4, 2)])
+    total = _abi.hygt_mixed_workspace_bytes(segs, 3)
+    parts = [_abi.hygt_workspace_bytes(100, 4, 2, 3), _abi.hygt_workspace_bytes(50, 6, 4, 35),
+             _abi.hygt_workspace_bytes(10, 8, 4, 2)]
+    assert total == sum((p + 255) // 256 * 256 for p in parts)
+    assert _abi.hygt_mixed_workspace_bytes(segs, 0) == 0
+    assert _abi.hygt_mixed_workspace_bytes(segs, 5) == 0
+    bad = _abi.segments([_seg(100, 1, 2, 3)])                 # N = 2 is not supported
+    assert _abi.hygt_mixed_workspace_bytes(bad, 1) == 0
+    assert _abi.hygt_mixed_plan(bad, 1, FAKE, 1 << 30, 0) == _abi.HYGT_EINVAL
+    assert _abi.hygt_mixed_plan(segs, 3, FAKE, total - 1, 0) == _abi.HYGT_EWORKSPACE
+    n = _abi.hygt_mixed_num_configs()
+    assert n >= 2
+    a = _abi.hygt_mixed_apply
+    assert a(segs, 3, 0, n, FAKE, total, 0) == _abi.HYGT_EINVAL          # config
+    assert a(segs, 3, 2, 0, FAKE, total, 0) == _abi.HYGT_EINVAL          # direction
+    assert a(segs, 3, 0, 0, FAKE + 4, total, 0) == _abi.HYGT_EWORKSPACE  # misaligned
+    ov = _abi.segments([_seg(100, 4, 2, 3, x=FAKE, y=FAKE + 64)])        # overlap
+    assert a(ov, 1, 0, 0, FAKE, 1 << 30, 0) == _abi.HYGT_EINVAL
+    st, h = _abi.hygt_mixed_graph_create(segs, 3, 0, 0, FAKE, total, 0)  # null stream
+    assert st == _abi.HYGT_EINVAL and h is None
+    assert _abi.hygt_graph_destroy(None) == _abi.HYGT_OK
+    assert _abi.hygt_graph_launch(None, 0) == _abi.HYGT_EINVAL
+    st, cfg, us = _abi.hygt_mixed_autotune(segs, 3, 0, FAKE, total - 1, 0)
+    assert st == _abi.HYGT_EWORKSPACE
