@@ -47,6 +47,7 @@ LOG2N = 6
 N = 1 << LOG2N
 ROUNDS = 4
 NCLASSES = 35
+HYGT_FWD = 0
 # algorithmic HBM bytes per block and direction: read N floats, write N floats,
 # read the 4-byte class index (angle tables are < 0.1% and not counted)
 BYTES_PER_BLOCK = 4 * N + 4 * N + 4
@@ -178,6 +179,80 @@ def _grad_step(torch, hygt, at, cs, xs, steps):
             "flops_per_call": NBLOCKS * ROUNDS * LOG2N * (N // 2) * 14}
 
 
+# Mixed-size workload: 4x4, 8x8 and 16x16 blocks in one batch.
+MIXED = [(2, 1 << 18, 2), (3, 1 << 17, 4), (4, 1 << 15, 4)]   # (log4 of N, blocks, rounds)
+MIXED_RING = 6   # distinct input sets (the whole batch would fit the last-level cache)
+
+
+def _mixed_workload(torch, hygt, steps):
+    """One batch of 2^18 4x4 (R = 2), 2^17 8x8 (R = 4) and 2^15 16x16 (R = 4)
+    separable AR(1) blocks (rho = 0.9), 35 classes per size. Per step, three
+    ways: the plain kernels (a plan and a launch per size), the mixed plan and
+    one persistent launch (autotuned launch shape), and a replay of the HIP
+    graph of the latter. Steps cycle over MIXED_RING input sets."""
+    from paper_2505_21728_amd import synth
+
+    dev = torch.device("cuda:0")
+    base = []
+    for i, (l4, nb, rounds) in enumerate(MIXED):
+        w = 1 << l4
+        d = 2 * l4
+        x = torch.from_numpy(synth.ar1_blocks(nb, w, seed=50 + i)).to(dev)
+        c = torch.from_numpy(synth.classes(nb, NCLASSES, seed=60 + i)).to(dev)
+        a = torch.from_numpy(synth.angles(NCLASSES, rounds, d, seed=70 + i)).to(dev)
+        base.append((x, c, a))
+    sets = []
+    for k in range(MIXED_RING):
+        sets.append([(torch.roll(x, 7919 * k, 0).contiguous(),
+                      torch.roll(c, 7919 * k, 0).contiguous(), a) for x, c, a in base])
+    batches = [hygt.MixedBatch(segs) for segs in sets]
+    cfg, tuned_us = batches[0].autotune(HYGT_FWD)
+    for b in batches:
+        b.config = cfg
+        b.plan()
+    graphs = [b.graph(HYGT_FWD) for b in batches]
+    plain_ws = [[torch.empty(hygt.workspace_bytes(x.shape[0], int(a.shape[2]), int(a.shape[1]),
+                                                  NCLASSES), dtype=torch.uint8, device=dev)
+                 for x, _, a in segs] for segs in sets]
+
+    def plain(k):
+        for (x, c, a), ws, y in zip(sets[k], plain_ws[k], batches[k].y):
+            hygt.Plan(a, c, workspace=ws).forward(x, out=y)
+
+    def fused(k):
+        batches[k].plan()
+        batches[k].apply(HYGT_FWD)
+
+    def graph(k):
+        graphs[k].launch()
+
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("plain", plain), ("fused", fused), ("graph", graph)):
+        for k in range(MIXED_RING):
+            fn(k)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            fn(i % MIXED_RING)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) * 1e3 / steps
+    for g in graphs:
+        g.close()
+    nblocks = sum(nb for _, nb, _ in MIXED)
+    nbytes = sum(nb * (8 * (1 << (2 * l4)) + 4) for l4, nb, _ in MIXED)
+    best = min(out.values())
+    return {"workload": "2^18 4x4 (R=2) + 2^17 8x8 (R=4) + 2^15 16x16 (R=4), 35 classes each, "
+                        "AR(1) rho=0.9, forward, plan included",
+            "us_per_step": out, "autotuned_config": cfg, "autotune_us": tuned_us,
+            "blocks": nblocks, "bytes_per_step": nbytes,
+            "best_blocks_per_s": nblocks / (best / 1e6),
+            "best_gbps": nbytes / (best / 1e6) / 1e9}
+
+
 def _cpu_baseline(x, cls, ang, sample):
     from oracle import hygt_oracle as orc
 
@@ -265,6 +340,7 @@ def main():
 
     klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
     grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
+    mixed = _mixed_workload(torch, hygt, args.steps)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -299,6 +375,7 @@ def main():
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
         "klt_dense": klt,
         "grad_step": grad,
+        "mixed": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

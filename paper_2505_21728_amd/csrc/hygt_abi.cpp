@@ -4,6 +4,7 @@
 
 #include "hygt.h"
 
+#include <algorithm>
 #include <cstdint>
 #include <new>
 #include <vector>
@@ -154,8 +155,15 @@ int mixed_args(const hygt_segment* segs, int nseg, const void* ws, size_t ws_byt
     const size_t total = mixed_layout(segs, nseg, offsets);
     if (ws == nullptr || ws_bytes < total || !aligned(ws, 256)) return HYGT_EWORKSPACE;
     *a = hygt::MixedArgs{};
+    // Items of the largest blocks go first: their tiles take longest, and
+    // the shorter ones then fill in behind them instead of trailing.
+    int order[HYGT_MAX_SEGMENTS];
+    for (int i = 0; i < nseg; ++i) order[i] = i;
+    std::stable_sort(order, order + nseg,
+                     [&](int p, int q) { return segs[p].log2n > segs[q].log2n; });
     int64_t item = 0;
-    for (int i = 0; i < nseg; ++i) {
+    for (int o = 0; o < nseg; ++o) {
+        const int i = order[o];
         const hygt_segment& g = segs[i];
         if (g.nblocks > 0) {
             if (g.x == nullptr || g.y == nullptr) return HYGT_EINVAL;
@@ -165,7 +173,7 @@ int mixed_args(const hygt_segment* segs, int nseg, const void* ws, size_t ws_byt
         const WsLayout l = hygt::ws_layout(g.nblocks, g.log2n, g.rounds, g.nclasses);
         void* part = static_cast<char*>(const_cast<void*>(ws)) + offsets[i];
         const hygt::WsPtrs p = hygt::ws_ptrs(part, l);
-        hygt::MixedSeg& m = a->seg[i];
+        hygt::MixedSeg& m = a->seg[o];
         m.x = g.x;
         m.y = g.y;
         m.nblocks = g.nblocks;

@@ -56,7 +56,7 @@ using namespace tile;
 // One pass along hypercube dimension K: each pair (m, n) gets the lifting
 // steps a += p b, b += q a, a += p b, in place (three FMAs, no temporary).
 template <int D, int K, int T>
-__device__ __forceinline__ void pass_lift(float (&v)[T][1 << D], const float* __restrict__ cp) {
+__device__ __forceinline__ void pass_lift(float (&v)[T][1 << D], ctab_f cp) {
     StaticFor<0, (1 << D) / 2>::run([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         constexpr int m = ins0(j, K);
@@ -76,9 +76,8 @@ __device__ __forceinline__ void pass_lift(float (&v)[T][1 << D], const float* __
 // round; inverse: k = D-1..0), then the final signs. RT > 0 unrolls the
 // rounds at compile time (RT == R); RT == 0 loops over `rounds`.
 template <int D, int DIR, int RT, int T>
-__device__ __forceinline__ void run_passes(float (&v)[T][1 << D], const float* __restrict__ tbl,
-                                           const float* __restrict__ sign, int has_neg,
-                                           int rounds) {
+__device__ __forceinline__ void run_passes(float (&v)[T][1 << D], ctab_f tbl, ctab_f sign,
+                                           int has_neg, int rounds) {
     constexpr int N = 1 << D;
     auto one_round = [&](int r) {
         StaticFor<0, D>::run([&](auto kk) {
@@ -111,7 +110,7 @@ __device__ __forceinline__ void run_passes(float (&v)[T][1 << D], const float* _
 // guarantees that both wavefronts have read part g before either overwrites
 // its buffer. Every wavefront of the workgroup passes the same barriers.
 template <int V>
-__device__ __forceinline__ void cross_pass(float (&v)[V], const float* __restrict__ cp,
+__device__ __forceinline__ void cross_pass(float (&v)[V], ctab_f cp,
                                            unsigned hbit, float4* xo, const float4* xp,
                                            int lane) {
     StaticFor<0, V / 16>::run([&](auto gg) {
@@ -152,8 +151,8 @@ __device__ __forceinline__ void cross_pass(float (&v)[V], const float* __restric
 // signs of elements 64q .. 64q + 63. The tile's wavefronts have consecutive
 // LDS areas of 512 float4 starting at `area0`.
 template <int D, int DIR>
-__device__ __forceinline__ void run_passes_split(float (&v)[1][64], const float* __restrict__ tbl,
-                                                 const float* __restrict__ sign, int has_neg,
+__device__ __forceinline__ void run_passes_split(float (&v)[1][64], ctab_f tbl, ctab_f sign,
+                                                 int has_neg,
                                                  int rounds, int q, float4* area0,
                                                  int lane) {
     constexpr int N = 1 << D;
@@ -161,7 +160,7 @@ __device__ __forceinline__ void run_passes_split(float (&v)[1][64], const float*
     for (int r = 0; r < rounds; ++r) {
         StaticFor<0, D>::run([&](auto kk) {
             constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
-            const float* cp = tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N;
+            ctab_f cp = tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N;
             if constexpr (K >= kLaneBits) {
                 constexpr int b = K - kLaneBits;
                 const int qq = ((q >> (b + 1)) << b) | (q & ((1 << b) - 1));
@@ -221,22 +220,35 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
 
     const size_t passes = static_cast<size_t>(rounds) * D;
     const size_t table = static_cast<size_t>(DIR) * nclasses + (c < 0 ? 0 : c);
+    // Touch every 128-byte line of the class's multiplier table once, spread
+    // over the lanes, so that the whole table is on its way into L2 before
+    // the passes' scalar loads ask for it line by line. It matters when a
+    // launch has few tiles per class and large tables (N = 256: 32 KB per
+    // class and direction, far beyond the scalar cache), where each pass
+    // would otherwise wait for memory in turn.
+    float touch = 0.0f;
+    {
+        ctab_f tb = as_ctab(coef) + table * passes * N;
+        const int lines = static_cast<int>((passes * N * sizeof(float) + 127) / 128);
+        for (int i = lane; i < lines; i += 64) touch += tb[i * 32];
+    }
     if constexpr (G::SPLIT) {
-        run_passes_split<D, DIR>(v, coef + table * passes * N, signs + table * N, modes[table],
-                                 rounds, q, area0, lane);
+        run_passes_split<D, DIR>(v, as_ctab(coef) + table * passes * N, as_ctab(signs) + table * N,
+                                 as_ctab(modes)[table], rounds, q, area0, lane);
         // The partners' last reads of this wavefront's exchange area come
         // before the stores below reuse it for staging.
         __syncthreads();
     } else {
-        run_passes<D, DIR, RT, T>(v, coef + table * passes * N, signs + table * N,
-                                  modes[table], rounds);
+        run_passes<D, DIR, RT, T>(v, as_ctab(coef) + table * passes * N,
+                                  as_ctab(signs) + table * N, as_ctab(modes)[table], rounds);
     }
 
     // Addresses for the way out are derived again from the block ids and the
     // lane index, made opaque here so that the compiler does not keep the
-    // ones of the way in alive (in registers) across the passes.
+    // ones of the way in alive (in registers) across the passes. The table
+    // touches are consumed here too, so that they are not dropped.
     int lane2 = lane;
-    asm volatile("" : "+v"(lane2));
+    asm volatile("" : "+v"(lane2) : "v"(touch));
     const int sw2 = swz<CHP>(lane2);
     StaticFor<0, T>::run([&](auto uu) {
         constexpr int u = decltype(uu)::value;
@@ -295,8 +307,8 @@ __global__ __launch_bounds__(64 * kWaves) void rotate_kernel_n2(
         if (blk < 0) continue;
         const float2 in = *reinterpret_cast<const float2*>(x + static_cast<int64_t>(blk) * 2);
         float v[1][2] = {{in.x, in.y}};
-        run_passes<1, DIR, 0, 1>(v, coef + table * rounds * 2, signs + table * 2, modes[table],
-                                 rounds);
+        run_passes<1, DIR, 0, 1>(v, as_ctab(coef) + table * rounds * 2, as_ctab(signs) + table * 2,
+                                 as_ctab(modes)[table], rounds);
         *reinterpret_cast<float2*>(y + static_cast<int64_t>(blk) * 2) =
             make_float2(v[0][0], v[0][1]);
     }
@@ -386,13 +398,13 @@ __device__ __forceinline__ void mixed_item(const MixedSeg& g, int64_t local, int
         const int first = wv & ~(S - 1);  // first wavefront of this tile
         const int64_t t0 = local * (4 / S) + wv / S;
         int c = -1;  // a dummy tile still joins the workgroup's barriers
-        if (t0 < g.max_tiles) c = __builtin_amdgcn_readfirstlane(g.tile_class[t0]);
+        if (t0 < g.max_tiles) c = __builtin_amdgcn_readfirstlane(as_ctab(g.tile_class)[t0]);
         rotate_tile<D, DIR, 0>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, wv - first,
                                g.perm, g.modes, g.coef, g.signs, lds[wv], lds[first], lane);
     } else {
         const int64_t t0 = local * 4 + wv;
         if (t0 >= g.max_tiles) return;
-        const int c = __builtin_amdgcn_readfirstlane(g.tile_class[t0]);
+        const int c = __builtin_amdgcn_readfirstlane(as_ctab(g.tile_class)[t0]);
         if (c < 0) return;
         if constexpr (UNROLL && D <= 6) {
             switch (g.rounds) {
@@ -420,45 +432,73 @@ __device__ __forceinline__ void mixed_item(const MixedSeg& g, int64_t local, int
     }
 }
 
-// Workgroups take items blockIdx.x, blockIdx.x + gridDim.x, ... of the
-// concatenated item lists of the segments. Every wavefront of a workgroup
-// walks the same items, so the N = 256 pairs always meet at the same
-// barriers.
+// Each segment's items are split into kXcds contiguous shares, one per XCD
+// (workgroups are dispatched round-robin over the XCDs, so workgroup w runs
+// on XCD w mod 8): the class-sorted tiles of a share cover few classes, whose
+// tables then stay in that XCD's caches. An XCD's shares of all segments,
+// largest blocks first, form one list whose entries its P = gridDim / 8
+// workgroups take in turn, so items of different sizes run side by side.
+// Every wavefront of a workgroup walks the same items, so wavefronts sharing
+// a tile meet at the same barriers.
+__device__ __forceinline__ int64_t share_lo(int64_t items, int64_t xcd) {
+    return items * xcd / kXcds;
+}
+
 template <int DIR, bool UNROLL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixedWavesPerSimd)))
 void mixed_kernel(MixedArgs a) {
     __shared__ float4 lds[4][512];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t item = blockIdx.x; item < a.total_items; item += gridDim.x) {
-        // the segment, chosen with constant indices so that its fields stay
-        // kernel-argument loads
-        MixedSeg g = a.seg[0];
-        StaticFor<1, kMaxSegments>::run([&](auto ss) {
+    const int64_t xcd = blockIdx.x % kXcds;
+    const int64_t P = gridDim.x / kXcds;
+    int64_t total = 0;  // entries of this XCD's list
+    StaticFor<0, kMaxSegments>::run([&](auto ss) {
+        constexpr int k = decltype(ss)::value;
+        if (k < a.nseg)
+            total += share_lo(a.seg[k].items, xcd + 1) - share_lo(a.seg[k].items, xcd);
+    });
+    for (int64_t e = blockIdx.x / kXcds; e < total; e += P) {
+        int64_t off = 0;
+        StaticFor<0, kMaxSegments>::run([&](auto ss) {
             constexpr int k = decltype(ss)::value;
-            if (k < a.nseg && item >= a.seg[k].item_begin) g = a.seg[k];
+            if (k >= a.nseg) return;
+            const MixedSeg& g = a.seg[k];
+            const int64_t lo = share_lo(g.items, xcd);
+            const int64_t len = share_lo(g.items, xcd + 1) - lo;
+            if (e >= off && e < off + len) {
+                const int64_t item = lo + (e - off);
+                switch (g.log2n) {
+                    case 2: mixed_item<2, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    case 3: mixed_item<3, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    case 4: mixed_item<4, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    case 5: mixed_item<5, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    case 6: mixed_item<6, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    case 7: mixed_item<7, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    case 8: mixed_item<8, DIR, UNROLL>(g, item, wv, lane, lds); break;
+                    default: break;
+                }
+            }
+            off += len;
         });
-        const int64_t local = item - g.item_begin;
-        switch (g.log2n) {
-            case 2: mixed_item<2, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            case 3: mixed_item<3, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            case 4: mixed_item<4, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            case 5: mixed_item<5, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            case 6: mixed_item<6, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            case 7: mixed_item<7, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            case 8: mixed_item<8, DIR, UNROLL>(g, local, wv, lane, lds); break;
-            default: break;
-        }
     }
 }
 
 // Configuration k: bit 0 = rounds unrolled; bits 1-2 = grid: one workgroup
-// per item, or 1, 2 or 4 waves of resident workgroups walking the items.
+// per list entry, or 1, 2 or 4 waves of resident workgroups striding through
+// the lists. Grids are multiples of 8.
 template <int DIR>
 hipError_t launch_mixed_dir(const MixedArgs& a, int config, hipStream_t stream) {
     const bool unroll = config & 1;
     const int grid_mode = (config >> 1) & 3;
-    int64_t grid = a.total_items;
+    int64_t per_xcd = 0;  // longest list of any XCD
+    for (int64_t x = 0; x < kXcds; ++x) {
+        int64_t n = 0;
+        for (int k = 0; k < a.nseg; ++k)
+            n += a.seg[k].items * (x + 1) / kXcds - a.seg[k].items * x / kXcds;
+        per_xcd = std::max(per_xcd, n);
+    }
+    int64_t grid = per_xcd * kXcds;
     if (grid_mode > 0) {
         const int64_t resident = static_cast<int64_t>(kComputeUnits) * kMixedWgPerCu;
         grid = std::min<int64_t>(grid, resident << (grid_mode - 1));

@@ -45,6 +45,16 @@ __device__ __forceinline__ int swz(int b) {
     else return 0;
 }
 
+// Read-only tables (multipliers, signs, modes) seen through the constant
+// address space: loads from it are known not to be clobbered by the
+// kernel's stores, so wave-uniform ones become scalar loads through the
+// scalar cache even where the compiler cannot prove it from the pointers
+// alone (as in a kernel that takes them from a struct of arguments).
+typedef const __attribute__((address_space(4))) float* ctab_f;
+typedef const __attribute__((address_space(4))) int32_t* ctab_i;
+__device__ __forceinline__ ctab_f as_ctab(const float* p) { return (ctab_f)p; }
+__device__ __forceinline__ ctab_i as_ctab(const int32_t* p) { return (ctab_i)p; }
+
 __device__ __forceinline__ int valid_block(int b, int64_t nblocks) {
     return (b >= 0 && b < nblocks) ? b : -1;  // never touch memory outside x / y
 }
