@@ -253,6 +253,37 @@ def _mixed_workload(torch, hygt, steps):
             "best_gbps": nbytes / (best / 1e6) / 1e9}
 
 
+SERVE_RATE = 2000.0      # requests per second (Poisson arrivals)
+SERVE_REQUESTS = 2000    # about one second of arrivals
+
+
+def _serve_workload(torch):
+    """Continuous batching of forward-transform requests arriving as a Poisson
+    process: each request a frame of 64 to 8192 blocks (log-uniform) of one
+    size, sizes 4x4 : 8x8 : 16x16 = 8 : 4 : 1, separable AR(1) residuals with
+    rho uniform in [0.7, 0.95] per block, 35 classes per size."""
+    import numpy as np
+
+    from paper_2505_21728_amd import serve, synth
+
+    dev = torch.device("cuda:0")
+    tables, pools = {}, {}
+    for i, (d, _) in enumerate(serve.SERVE_MIX):
+        rounds = 2 if d == 4 else 4
+        tables[d] = torch.from_numpy(synth.angles(NCLASSES, rounds, d, seed=80 + i)).to(dev)
+        n = 1 << 15
+        rho = np.random.default_rng(90 + i).uniform(0.7, 0.95, n)
+        pools[d] = torch.from_numpy(synth.ar1_blocks(n, 1 << (d // 2), rho=rho,
+                                                     seed=95 + i)).to(dev)
+    srv = serve.Server(tables, capacity={4: 1 << 15, 6: 1 << 15, 8: 1 << 14}, slots=3)
+    reqs = serve.make_requests(SERVE_REQUESTS, tables, pools, seed=4)
+    torch.cuda.synchronize()
+    stats = serve.run_poisson(srv, reqs, SERVE_RATE)
+    stats["workload"] = ("Poisson 2000 req/s, 64..8192 blocks per request (log-uniform), "
+                         "4x4:8x8:16x16 = 8:4:1, forward, 3 slots")
+    return stats
+
+
 def _cpu_baseline(x, cls, ang, sample):
     from oracle import hygt_oracle as orc
 
@@ -341,6 +372,7 @@ def main():
     klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
     grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
     mixed = _mixed_workload(torch, hygt, args.steps)
+    served = _serve_workload(torch)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -376,6 +408,7 @@ def main():
         "klt_dense": klt,
         "grad_step": grad,
         "mixed": mixed,
+        "serve": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

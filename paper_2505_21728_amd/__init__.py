@@ -260,7 +260,7 @@ class MixedBatch:
     plan(), apply() and graph replays read and write them in place.
     """
 
-    def __init__(self, segments, stream=None):
+    def __init__(self, segments, stream=None, workspace=None, config=0):
         torch = _torch()
         _require(1 <= len(segments) <= _abi.HYGT_MAX_SEGMENTS,
                  f"1 to {_abi.HYGT_MAX_SEGMENTS} segments")
@@ -296,9 +296,14 @@ class MixedBatch:
         self._n = len(items)
         self.ws_bytes = _abi.hygt_mixed_workspace_bytes(self._segs, self._n)
         _require(self.ws_bytes > 0, "invalid segment sizes")
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        _require(workspace.is_cuda and workspace.dtype == torch.uint8 and
+                 workspace.numel() >= self.ws_bytes and workspace.data_ptr() % 256 == 0,
+                 "workspace too small or misaligned")
+        self.workspace = workspace
         self._stream = stream
-        self.config = 0
+        self.config = config
         self.plan()
 
     def _s(self, stream):
