@@ -116,6 +116,18 @@ int hygt_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
               const float* angles, int nclasses,
               void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* hygt_plan() with the parameters given as 8-bit codes (Fig. 6: one byte per
+ * parameter, converted to multipliers only when needed; the paper does not
+ * give the code-to-angle map): code q stands for the angle
+ * (q - 128) * pi / 128, so 256 codes cover [-pi, pi) in equal steps and
+ * q = 128 is the zero angle. codes: uint8 [nclasses][rounds][log2n][N/2].
+ * The multipliers are computed from the exact angle in FP64, so a plan from
+ * codes equals a plan from the FP32 angles closest to those angles only to
+ * within the FP32 rounding of the angle. */
+int hygt_plan_codes(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
+                    const uint8_t* codes, int nclasses,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Applies the planned transform (direction HYGT_FORWARD or HYGT_INVERSE) to
  * x, writing y. The sizes must be those given to the hygt_plan() call that
  * filled the workspace; the plan may be applied any number of times, in both
@@ -123,6 +135,20 @@ int hygt_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
 int hygt_apply(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                int nclasses, int direction,
                const void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Largest block length (log2) of hygt_apply_perm(). */
+#define HYGT_PERM_MAX_LOG2N 6
+
+/* hygt_apply() with the optional final permutation pass of Fig. 4, which
+ * orders each class's coefficients (by variance, in the paper):
+ *   forward:  y[b][i] = (T_c x[b])[perm[c][i]];
+ *   inverse:  undoes that permutation, then applies T_c^T.
+ * perm: int32 [nclasses][N], each row a permutation of 0..N-1 (device
+ * memory; entries are used modulo N, so a bad row gives wrong results, never
+ * an access outside the block). 2 <= log2n <= HYGT_PERM_MAX_LOG2N. */
+int hygt_apply_perm(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                    int nclasses, int direction, const int32_t* perm,
+                    const void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* hygt_plan() followed by hygt_apply(HYGT_FORWARD): y[b] = T_{cls[b]} x[b]. */
 int hygt_forward(const float* x, float* y, const int32_t* cls, int64_t nblocks,

@@ -56,6 +56,11 @@ __all__ = [
     "class_log_variance_loss",
     "class_log_variance_grad",
     "backward",
+    "angles_from_codes",
+    "codes_from_angles",
+    "forward_permuted",
+    "inverse_permuted",
+    "variance_order",
 ]
 
 
@@ -362,6 +367,68 @@ def backward(y, gy, cls, angles):
             g[:, m] = c * gm - s * gn
             g[:, n] = s * gm + c * gn
     return g, gangles
+
+
+# ---------------------------------------------------------------------------
+# Paper variants: 8-bit parameter codes (Fig. 6) and the permutation pass (Fig. 4)
+# ---------------------------------------------------------------------------
+
+def angles_from_codes(codes) -> np.ndarray:
+    """Angle of each 8-bit code: (q - 128) * pi / 128.
+
+    Fig. 6 stores one byte per parameter and a shared table of multipliers;
+    the paper does not give the code-to-angle map (parity unpinned for the
+    map itself). This reading spaces the 256 codes evenly over [-pi, pi),
+    with q = 128 the zero angle.
+    """
+    q = np.asarray(codes, dtype=np.int64)
+    return (q - 128).astype(np.float64) * (math.pi / 128.0)
+
+
+def codes_from_angles(angles) -> np.ndarray:
+    """Nearest 8-bit code of each angle (angles taken modulo 2 pi)."""
+    a = np.asarray(angles, dtype=np.float64)
+    q = np.rint(a * (128.0 / math.pi)).astype(np.int64) + 128
+    return np.mod(q, 256).astype(np.uint8)
+
+
+def forward_permuted(x, cls, angles, perm) -> np.ndarray:
+    """forward() followed by the permutation pass of Fig. 4: output position
+    i of a block of class c holds transform coefficient perm[c, i]."""
+    y = forward(x, cls, angles)
+    cls = np.zeros(y.shape[0], dtype=np.int64) if cls is None else np.asarray(cls, np.int64)
+    perm = np.asarray(perm, dtype=np.int64)
+    out = np.empty_like(y)
+    for b in range(y.shape[0]):
+        out[b] = y[b, perm[cls[b]]]
+    return out
+
+
+def inverse_permuted(yp, cls, angles, perm) -> np.ndarray:
+    """Inverse of forward_permuted(): undo the permutation, then inverse()."""
+    yp = np.asarray(yp, dtype=np.float64)
+    cls_i = np.zeros(yp.shape[0], dtype=np.int64) if cls is None else np.asarray(cls, np.int64)
+    perm = np.asarray(perm, dtype=np.int64)
+    y = np.empty_like(yp)
+    for b in range(yp.shape[0]):
+        y[b, perm[cls_i[b]]] = yp[b]
+    return inverse(y, cls, angles)
+
+
+def variance_order(y, cls, nclasses: int) -> np.ndarray:
+    """Per class, the coefficients sorted by decreasing variance (mean of
+    y^2 over the class's blocks), ties by index: the sort of Fig. 4's
+    optional permutation pass. Classes without blocks keep the identity."""
+    y = np.asarray(y, dtype=np.float64)
+    cls = np.asarray(cls, dtype=np.int64)
+    n = y.shape[1]
+    out = np.tile(np.arange(n, dtype=np.int64), (nclasses, 1))
+    for c in range(nclasses):
+        rows = y[cls == c]
+        if rows.shape[0]:
+            var = np.mean(rows * rows, axis=0)
+            out[c] = np.lexsort((np.arange(n), -var))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -6,7 +6,7 @@ All computation runs in the HIP kernels of libhygt.so (include/hygt.h); this
 module checks tensor arguments and passes device pointers and the current
 stream through the C ABI. PyTorch provides device memory and streams only.
 
-    plan = Plan(angles, cls)          # angles [C, R, d, N/2] f32, cls [B] i32 (cuda)
+    plan = Plan(angles, cls)          # angles [C, R, d, N/2] f32 (or u8 codes), cls [B] i32
     y = plan.forward(x)               # x [B, N] f32 (cuda): y[b] = T_cls[b] x[b]
     z = plan.inverse(y)               # z[b] = T_cls[b]^T y[b]
 """
@@ -57,7 +57,8 @@ class Plan:
         torch = _torch()
         _require(isinstance(angles, torch.Tensor), "angles must be a torch.Tensor", TypeError)
         _require(angles.is_cuda, "angles must be on a HIP device")
-        _require(angles.dtype == torch.float32, "angles must be float32", TypeError)
+        _require(angles.dtype in (torch.float32, torch.uint8),
+                 "angles must be float32 radians or uint8 codes", TypeError)
         _require(angles.dim() == 4, "angles must be [nclasses, rounds, log2n, N/2]")
         _require(angles.is_contiguous(), "angles must be contiguous")
         nclasses, rounds, log2n, half = (int(s) for s in angles.shape)
@@ -93,10 +94,11 @@ class Plan:
         _require(workspace.data_ptr() % 256 == 0, "workspace must be 256-byte aligned")
         self.workspace = workspace
         self._stream = stream
+        plan_fn = _abi.hygt_plan_codes if angles.dtype == torch.uint8 else _abi.hygt_plan
         with torch.cuda.device(self.device):
-            st = _abi.hygt_plan(0 if cls is None else cls.data_ptr(), self.nblocks, log2n,
-                                rounds, angles.data_ptr(), nclasses, workspace.data_ptr(),
-                                self.ws_bytes, _stream_handle(stream))
+            st = plan_fn(0 if cls is None else cls.data_ptr(), self.nblocks, log2n,
+                         rounds, angles.data_ptr(), nclasses, workspace.data_ptr(),
+                         self.ws_bytes, _stream_handle(stream))
         _abi._check(st, "hygt_plan")
 
     def _check_x(self, x):
@@ -133,6 +135,28 @@ class Plan:
     def inverse(self, x, out=None, stream=None):
         """y[b] = T_{cls[b]}^T x[b] (eq. (6) and (9))."""
         return self.apply(x, HYGT_INVERSE, out, stream)
+
+    def apply_permuted(self, x, direction: int, perm, out=None, stream=None):
+        """The transform with the permutation pass of Fig. 4: perm [C, N]
+        int32 rows give, for each output position, its source coefficient
+        (forward); the inverse undoes it first. N <= 64."""
+        torch = _torch()
+        self._check_x(x)
+        _require(isinstance(perm, torch.Tensor) and perm.dtype == torch.int32 and
+                 perm.is_contiguous() and perm.device == self.device and
+                 tuple(perm.shape) == (self.nclasses, self.n), "perm must be [C, N] int32")
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            self._check_x(out)
+        s = stream if stream is not None else self._stream
+        with torch.cuda.device(self.device):
+            st = _abi.hygt_apply_perm(x.data_ptr(), out.data_ptr(), self.nblocks, self.log2n,
+                                      self.rounds, self.nclasses, direction, perm.data_ptr(),
+                                      self.workspace.data_ptr(), self.ws_bytes,
+                                      _stream_handle(s))
+        _abi._check(st, "hygt_apply_perm")
+        return out
 
     def dense(self, x, mats, out=None):
         """y[b] = M_{cls[b]} x[b] with BF16 matrices mats [C, N, N] on the

@@ -49,6 +49,11 @@ _SIGNATURES = {
     "hygt_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int, _c.c_int, _c.c_int]),
     "hygt_plan": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int, _c.c_void_p,
                              _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_apply_perm": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
+                                   _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                   _c.c_void_p]),
+    "hygt_plan_codes": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int, _c.c_void_p,
+                                   _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_apply": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
                               _c.c_int, _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_forward": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int,
@@ -133,6 +138,18 @@ def hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr, ws_
               stream) -> int:
     return load().hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
                             ws_bytes, stream)
+
+
+def hygt_apply_perm(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, perm_ptr, ws_ptr,
+                    ws_bytes, stream) -> int:
+    return load().hygt_apply_perm(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction,
+                                  perm_ptr, ws_ptr, ws_bytes, stream)
+
+
+def hygt_plan_codes(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr, ws_bytes,
+                    stream) -> int:
+    return load().hygt_plan_codes(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr,
+                                  ws_bytes, stream)
 
 
 def hygt_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr, ws_bytes,

@@ -37,18 +37,25 @@ bool overlap_ok(const float* x, const float* y, int64_t nblocks, int log2n) {
     return xa + bytes <= ya || ya + bytes <= xa;
 }
 
-int plan_impl(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const float* angles,
-              int nclasses, void* ws, size_t ws_bytes, hipStream_t stream) {
+int plan_any(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const float* angles,
+             const uint8_t* codes, int nclasses, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!sizes_ok(nblocks, log2n, rounds, nclasses)) return HYGT_EINVAL;
     const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
     if (int s = check_workspace(ws, ws_bytes, l)) return s;
     if (nblocks == 0) return HYGT_OK;  // empty arrays may come as NULL pointers
-    if (angles == nullptr || !aligned(angles, 4)) return HYGT_EINVAL;
+    if (angles == nullptr && codes == nullptr) return HYGT_EINVAL;
+    if (angles != nullptr && !aligned(angles, 4)) return HYGT_EINVAL;
     if (cls == nullptr && nclasses != 1) return HYGT_EINVAL;
     if (cls != nullptr && !aligned(cls, 4)) return HYGT_EINVAL;
-    const hipError_t e = hygt::launch_plan(cls, nblocks, log2n, rounds, angles, nclasses, l,
-                                           hygt::ws_ptrs(ws, l), stream);
+    const hipError_t e = hygt::launch_plan(cls, nblocks, log2n, rounds, angles, codes, nclasses,
+                                           l, hygt::ws_ptrs(ws, l), stream);
     return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
+int plan_impl(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const float* angles,
+              int nclasses, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (nblocks > 0 && angles == nullptr) return HYGT_EINVAL;
+    return plan_any(cls, nblocks, log2n, rounds, angles, nullptr, nclasses, ws, ws_bytes, stream);
 }
 
 int apply_impl(const float* x, float* y, int64_t nblocks, int log2n, int rounds, int nclasses,
@@ -275,6 +282,32 @@ int hygt_dense_apply(const float* x, float* y, int64_t nblocks, int log2n, int r
                      size_t workspace_bytes, hipStream_t stream) {
     return dense_impl(x, y, nblocks, log2n, rounds, nclasses, mats, workspace, workspace_bytes,
                       stream);
+}
+
+int hygt_apply_perm(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                    int nclasses, int direction, const int32_t* perm, const void* workspace,
+                    size_t workspace_bytes, hipStream_t stream) {
+    if (!sizes_ok(nblocks, log2n, rounds, nclasses)) return HYGT_EINVAL;
+    if (log2n < 2 || log2n > HYGT_PERM_MAX_LOG2N) return HYGT_EINVAL;
+    if (direction != HYGT_FORWARD && direction != HYGT_INVERSE) return HYGT_EINVAL;
+    const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
+    if (int s = check_workspace(workspace, workspace_bytes, l)) return s;
+    if (nblocks == 0) return HYGT_OK;
+    if (x == nullptr || y == nullptr || perm == nullptr) return HYGT_EINVAL;
+    if (!aligned(x, 16) || !aligned(y, 16) || !aligned(perm, 4)) return HYGT_EINVAL;
+    if (!overlap_ok(x, y, nblocks, log2n)) return HYGT_EINVAL;
+    const hipError_t e = hygt::launch_rotate_perm(
+        x, y, nblocks, log2n, rounds, nclasses, direction, perm, l,
+        hygt::ws_ptrs(const_cast<void*>(workspace), l), stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
+int hygt_plan_codes(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
+                    const uint8_t* codes, int nclasses, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream) {
+    if (nblocks > 0 && codes == nullptr) return HYGT_EINVAL;
+    return plan_any(cls, nblocks, log2n, rounds, nullptr, codes, nclasses, workspace,
+                    workspace_bytes, stream);
 }
 
 size_t hygt_mixed_workspace_bytes(const hygt_segment* segs, int nseg) {

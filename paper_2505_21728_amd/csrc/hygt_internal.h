@@ -121,13 +121,19 @@ inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
 
 // Kernel launchers (hygt_plan.hip, hygt_rotate.hip, hygt_backward.hip, hygt_dense.hip). Each returns the
 // hipError_t of its launches.
+// Exactly one of angles (FP32 radians) and codes (8-bit codes) is non-NULL.
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
-                       const float* angles, int nclasses, const WsLayout& l,
-                       const WsPtrs& p, hipStream_t stream);
+                       const float* angles, const uint8_t* codes, int nclasses,
+                       const WsLayout& l, const WsPtrs& p, hipStream_t stream);
 
 hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                          int nclasses, int direction, const WsLayout& l, const WsPtrs& p,
                          hipStream_t stream);
+
+// The transform with the permutation pass of Fig. 4 (hygt_rotate.hip), 4 <= N <= 64.
+hipError_t launch_rotate_perm(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                              int nclasses, int direction, const int32_t* outperm,
+                              const WsLayout& l, const WsPtrs& p, hipStream_t stream);
 
 // Reverse-mode derivative of the forward transform (hygt_backward.hip), N <= 64.
 hipError_t launch_backward(const float* y, const float* gy, float* gx, float* gangles,

@@ -112,7 +112,15 @@ __device__ inline PlaceLds place_lds(int* base, int64_t nchunks, int nclasses) {
 // Multiplier table of one (direction, class); see the file comment. The
 // FP64 conversion of a batch of angles runs in parallel; only the sign walk
 // through the passes is sequential.
+// Angle of 8-bit parameter code q (Fig. 6 keeps one byte per parameter and
+// a shared table of multipliers): q steps of 2 pi / 256 from -pi, so that
+// q = 128 is the zero angle. Exact in FP64.
+__device__ __forceinline__ double code_angle(uint8_t q) {
+    return (static_cast<double>(q) - 128.0) * (3.141592653589793238462643383279502884 / 128.0);
+}
+
 __device__ void build_table(TableShared& sh, int dir, int c, const float* __restrict__ angles,
+                            const uint8_t* __restrict__ codes,
                             int log2n, int rounds, int nclasses, float* __restrict__ coef,
                             float* __restrict__ signs, int32_t* __restrict__ modes) {
     const int tid = threadIdx.x;
@@ -134,8 +142,8 @@ __device__ void build_table(TableShared& sh, int dir, int c, const float* __rest
             const int kk = p % log2n, rr = p / log2n;
             const int k = dir ? log2n - 1 - kk : kk;
             const int r = dir ? rounds - 1 - rr : rr;
-            double th = static_cast<double>(
-                angles[((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + j]);
+            const size_t ai = ((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + j;
+            double th = codes != nullptr ? code_angle(codes[ai]) : static_cast<double>(angles[ai]);
             if (dir) th = -th;
             if (k >= kLaneBits) {  // (cos, sin) form, no reduction
                 sh.tanh_phi[e] = static_cast<float>(cos(th));
@@ -277,13 +285,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
     int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
     int32_t* __restrict__ tile_class, int32_t* __restrict__ perm,
-    const float* __restrict__ angles, int log2n, int rounds, int32_t* __restrict__ modes,
+    const float* __restrict__ angles, const uint8_t* __restrict__ codes, int log2n, int rounds,
+    int32_t* __restrict__ modes,
     float* __restrict__ coef, float* __restrict__ signs) {
     extern __shared__ __align__(16) int place_dyn[];
     if (blockIdx.x < 2 * nclasses) {
         const int wg = static_cast<int>(blockIdx.x);
         build_table(*reinterpret_cast<TableShared*>(place_dyn), wg / nclasses, wg % nclasses,
-                    angles, log2n, rounds, nclasses, coef, signs, modes);
+                    angles, codes, log2n, rounds, nclasses, coef, signs, modes);
         return;
     }
     const PlaceLds sh = place_lds(place_dyn, nchunks, nclasses);
@@ -400,8 +409,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
 }  // namespace
 
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
-                       const float* angles, int nclasses, const WsLayout& l,
-                       const WsPtrs& p, hipStream_t stream) {
+                       const float* angles, const uint8_t* codes, int nclasses,
+                       const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
     hipLaunchKernelGGL(plan_count_kernel, dim3(static_cast<unsigned>(l.nchunks)),
                        dim3(kPlanThreads), 0, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
                        p.hdr, p.chunk_err, p.counts);
@@ -416,8 +425,8 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
     }
     hipLaunchKernelGGL(plan_place_kernel, dim3(static_cast<unsigned>(2 * nclasses + l.nchunks)),
                        dim3(kPlanThreads), lds, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
-                       l.max_tiles, p.counts, p.tile_class, p.perm, angles, log2n, rounds,
-                       p.modes, p.coef, p.signs);
+                       l.max_tiles, p.counts, p.tile_class, p.perm, angles, codes, log2n,
+                       rounds, p.modes, p.coef, p.signs);
     return hipGetLastError();
 }
 

@@ -6,13 +6,19 @@
 // butterfly of every pass is a register-to-register operation with
 // compile-time register indices, and the class's per-pass multipliers are
 // wave-uniform, so they arrive through scalar loads as SGPR operands of the
-// FMAs. Nothing is exchanged between lanes during the passes. For N = 256 a
-// lane's registers cannot hold a block, so two wavefronts share the tile,
-// wavefront h holding values 128h .. 128h+127 of every block; the passes
-// along bit 7 pair the two halves, which swap values through LDS in parts of
-// 16 per lane.
+// FMAs. Nothing is exchanged between lanes during the passes. A lane holds
+// at most 64 values, so for N = 128 and N = 256 two and four wavefronts share
+// the tile, wavefront q holding values 64q .. 64q+63 of every block; the
+// passes along bits 6 and 7 pair values of two wavefronts, which swap them
+// through double-buffered LDS areas in parts of 16 per lane and rotate with
+// (cos, sin) multipliers instead of the lifting steps.
 //
-// Memory. Each lane loads its own block (for N = 256, its half of the block)
+// Variants. The permutation pass of Fig. 4 (N <= 64) reorders each lane's
+// row through a per-wavefront LDS row area after the passes (forward) or
+// before them (inverse). The fused launch for batches of several block
+// sizes (mixed_kernel) runs the same tile body over one persistent grid.
+//
+// Memory. Each lane loads its own block (for N > 64, its share of the block)
 // straight into registers, N / 4 loads of 16 bytes all in flight at once, so
 // the first passes start on the chunks that arrive first. The way out goes
 // through LDS: each lane writes its row, and the transposed slots go out so
@@ -179,6 +185,58 @@ __device__ __forceinline__ void run_passes_split(float (&v)[1][64], ctab_f tbl, 
     }
 }
 
+// Permutation pass (Fig. 4), N <= 64, through this wavefront's row area R of
+// 64 rows of N floats: chunk q of lane l's row sits at slot
+// l * CH + (q ^ (l mod CH)), so that 16 consecutive lanes touch distinct
+// banks. Position p of the class's permutation row holds output p's source
+// coefficient; entries are masked to [0, N) so that no access leaves the row.
+template <int D>
+__device__ __forceinline__ int perm_addr(int lane, int p) {
+    constexpr int CH = (1 << D) / 4;
+    return 4 * (lane * CH + ((p >> 2) ^ (lane & (CH - 1)))) + (p & 3);
+}
+
+// Forward: v[j] <- v[perm[j]].
+template <int D>
+__device__ __forceinline__ void permute_row(float* v, float4* R, ctab_i perm, int lane) {
+    constexpr int N = 1 << D;
+    constexpr int CH = N / 4;
+    StaticFor<0, CH>::run([&](auto qq) {
+        constexpr int q = decltype(qq)::value;
+        R[lane * CH + (q ^ (lane & (CH - 1)))] =
+            make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    });
+    asm volatile("" ::: "memory");
+    const float* Rf = reinterpret_cast<const float*>(R);
+    StaticFor<0, N>::run([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        v[j] = Rf[perm_addr<D>(lane, perm[j] & (N - 1))];
+    });
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Inverse: v[perm[j]] <- v[j].
+template <int D>
+__device__ __forceinline__ void unpermute_row(float* v, float4* R, ctab_i perm, int lane) {
+    constexpr int N = 1 << D;
+    constexpr int CH = N / 4;
+    float* Rf = reinterpret_cast<float*>(R);
+    StaticFor<0, N>::run([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        Rf[perm_addr<D>(lane, perm[j] & (N - 1))] = v[j];
+    });
+    asm volatile("" ::: "memory");
+    StaticFor<0, CH>::run([&](auto qq) {
+        constexpr int q = decltype(qq)::value;
+        const float4 f = R[lane * CH + (q ^ (lane & (CH - 1)))];
+        v[4 * q + 0] = f.x;
+        v[4 * q + 1] = f.y;
+        v[4 * q + 2] = f.z;
+        v[4 * q + 3] = f.w;
+    });
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 // One tile of a transform of N >= 4: loads, passes, stores. For N >= 128
 // the tile belongs to 2^(D-6) wavefronts, this one (number q of them)
 // holding values 64q .. 64q+63 of every block; the tile's wavefronts have
@@ -192,7 +250,7 @@ __device__ __forceinline__ void run_passes_split(float (&v)[1][64], ctab_f tbl, 
 // completed, and no other wavefront touches it, so the restrict qualifiers
 // (which let the per-tile class loads stay scalar) hold for every pair of
 // accesses that the compiler could reorder.
-template <int D, int DIR, int RT>
+template <int D, int DIR, int RT, bool PERM = false>
 __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* __restrict__ y,
                                             int64_t nblocks, int rounds, int nclasses,
                                             int64_t t0, int c, int q,
@@ -200,7 +258,8 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
                                             const int32_t* __restrict__ modes,
                                             const float* __restrict__ coef,
                                             const float* __restrict__ signs, float4* L,
-                                            float4* area0, int lane) {
+                                            float4* area0, int lane,
+                                            ctab_i outperm = nullptr) {
     using G = TileGeo<D>;
     constexpr int N = G::N;
     constexpr int CHP = G::CHP;
@@ -218,6 +277,12 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
         load_row<D>(xh, blk[u], v[u]);
     });
 
+    // with the permutation pass, the inverse first puts the coefficients back
+    // in transform order (the row area is the staging area, 16 KB per wave)
+    if constexpr (PERM && DIR == 1)
+        StaticFor<0, T>::run([&](auto uu) {
+            unpermute_row<D>(v[decltype(uu)::value], L, outperm + c * N, lane);
+        });
     const size_t passes = static_cast<size_t>(rounds) * D;
     const size_t table = static_cast<size_t>(DIR) * nclasses + (c < 0 ? 0 : c);
     // Touch every 128-byte line of the class's multiplier table once, spread
@@ -241,6 +306,10 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
     } else {
         run_passes<D, DIR, RT, T>(v, as_ctab(coef) + table * passes * N,
                                   as_ctab(signs) + table * N, as_ctab(modes)[table], rounds);
+        if constexpr (PERM && DIR == 0)
+            StaticFor<0, T>::run([&](auto uu) {
+                permute_row<D>(v[decltype(uu)::value], L, outperm + c * N, lane);
+            });
     }
 
     // Addresses for the way out are derived again from the block ids and the
@@ -286,6 +355,26 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
     if (c < 0) return;  // past the last tile
     rotate_tile<D, DIR, RT>(x, y, nblocks, rounds, nclasses, t0, c, q, perm, modes, coef, signs,
                             lds[wv], lds[0], lane);
+}
+
+// N <= 64 with the permutation pass: as rotate_kernel, with a 16 KB row area
+// per wavefront for the permutation (the part staging reuses its start).
+template <int D, int DIR>
+__global__ __launch_bounds__(64 * kWaves) void rotate_perm_kernel(
+    const float* __restrict__ x, float* __restrict__ y, int64_t nblocks, int rounds,
+    int nclasses, int64_t max_tiles, const int32_t* __restrict__ tile_class,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ modes,
+    const float* __restrict__ coef, const float* __restrict__ signs,
+    const int32_t* __restrict__ outperm) {
+    __shared__ float4 lds[kWaves][64 * ((1 << D) / 4)];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    if (t0 >= max_tiles) return;
+    const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
+    if (c < 0) return;
+    rotate_tile<D, DIR, 0, true>(x, y, nblocks, rounds, nclasses, t0, c, 0, perm, modes, coef,
+                                 signs, lds[wv], lds[wv], lane, as_ctab(outperm));
 }
 
 // N == 2: one 8-byte block per lane, read and written directly.
@@ -523,6 +612,42 @@ int64_t mixed_items(int log2n, int64_t max_tiles) {
 hipError_t launch_mixed(const MixedArgs& a, int direction, int config, hipStream_t stream) {
     if (direction == 0) return launch_mixed_dir<0>(a, config, stream);
     return launch_mixed_dir<1>(a, config, stream);
+}
+
+namespace {
+template <int D, int DIR>
+hipError_t launch_perm_one(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
+                           const int32_t* outperm, const WsLayout& l, const WsPtrs& p,
+                           hipStream_t stream) {
+    const int64_t groups = (l.max_tiles + kWaves - 1) / kWaves;
+    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    hipLaunchKernelGGL((rotate_perm_kernel<D, DIR>), grid, dim3(64 * kWaves), 0, stream, x, y,
+                       nblocks, rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes,
+                       p.coef, p.signs, outperm);
+    return hipGetLastError();
+}
+
+template <int DIR>
+hipError_t launch_perm_dir(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                           int nclasses, const int32_t* outperm, const WsLayout& l,
+                           const WsPtrs& p, hipStream_t stream) {
+    switch (log2n) {
+        case 2: return launch_perm_one<2, DIR>(x, y, nblocks, rounds, nclasses, outperm, l, p, stream);
+        case 3: return launch_perm_one<3, DIR>(x, y, nblocks, rounds, nclasses, outperm, l, p, stream);
+        case 4: return launch_perm_one<4, DIR>(x, y, nblocks, rounds, nclasses, outperm, l, p, stream);
+        case 5: return launch_perm_one<5, DIR>(x, y, nblocks, rounds, nclasses, outperm, l, p, stream);
+        case 6: return launch_perm_one<6, DIR>(x, y, nblocks, rounds, nclasses, outperm, l, p, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_rotate_perm(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
+                              int nclasses, int direction, const int32_t* outperm,
+                              const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
+    if (direction == 0)
+        return launch_perm_dir<0>(x, y, nblocks, log2n, rounds, nclasses, outperm, l, p, stream);
+    return launch_perm_dir<1>(x, y, nblocks, log2n, rounds, nclasses, outperm, l, p, stream);
 }
 
 hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, int rounds,

@@ -118,6 +118,31 @@ def test_forward_inverse_reject_before_planning():
         assert fn(FAKE, FAKE * 8, FAKE, 0, 6, 4, FAKE, 35, FAKE, need, 0) == _abi.HYGT_OK
 
 
+def test_apply_perm_rejects():
+    need = _abi.hygt_workspace_bytes(100, 4, 2, 3)
+    a = _abi.hygt_apply_perm
+    x, y, p = FAKE, FAKE * 4, FAKE * 8
+    assert a(x, y, 100, 4, 2, 3, 0, 0, FAKE, need, 0) == _abi.HYGT_EINVAL      # perm NULL
+    assert a(x, y, 100, 4, 2, 3, 0, p + 2, FAKE, need, 0) == _abi.HYGT_EINVAL  # perm misaligned
+    assert a(x, y, 100, 4, 2, 3, 2, p, FAKE, need, 0) == _abi.HYGT_EINVAL      # direction
+    need7 = _abi.hygt_workspace_bytes(100, 7, 2, 3)
+    assert a(x, y, 100, 7, 2, 3, 0, p, FAKE, need7, 0) == _abi.HYGT_EINVAL     # N > 64
+    need1 = _abi.hygt_workspace_bytes(100, 1, 2, 3)
+    assert a(x, y, 100, 1, 2, 3, 0, p, FAKE, need1, 0) == _abi.HYGT_EINVAL     # N == 2
+    assert a(x, x + 64, 100, 4, 2, 3, 0, p, FAKE, need, 0) == _abi.HYGT_EINVAL  # overlap
+    assert a(x, y, 100, 4, 2, 3, 0, p, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert a(0, 0, 0, 4, 2, 3, 0, 0, FAKE, need, 0) == _abi.HYGT_OK             # empty no-op
+
+
+def test_plan_codes_rejects():
+    need = _abi.hygt_workspace_bytes(100, 4, 2, 3)
+    pc = _abi.hygt_plan_codes
+    assert pc(FAKE, 100, 4, 2, 0, 3, FAKE, need, 0) == _abi.HYGT_EINVAL        # codes NULL
+    assert pc(FAKE, 100, 9, 2, FAKE, 3, FAKE, need, 0) == _abi.HYGT_EINVAL     # log2n
+    assert pc(FAKE, 100, 4, 2, FAKE, 3, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert pc(FAKE + 1, 0, 4, 2, FAKE + 1, 3, FAKE, need, 0) == _abi.HYGT_OK    # no-op
+
+
 def test_dense_rejects():
     need = _abi.hygt_workspace_bytes(100, 6, 2, 3)
     d = _abi.hygt_dense_apply

@@ -505,3 +505,47 @@ def test_fd_pin_catches_backward_mutants(mutant):
     cls = rng.integers(0, 2, 20)
     bwd = _mutant_backward(**{mutant: True})
     assert _fd_loss_grads(x, cls, ang, 2, backward=bwd) > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Paper variants: 8-bit codes, permutation pass
+# ---------------------------------------------------------------------------
+
+def test_codes_map():
+    """The code map: q = 128 is zero, 64 and 192 are -/+ pi/2, 0 is -pi;
+    codes_from_angles inverts it on the code grid."""
+    a = orc.angles_from_codes(np.array([0, 64, 128, 192, 255], dtype=np.uint8))
+    assert np.allclose(a, [-math.pi, -math.pi / 2, 0.0, math.pi / 2, math.pi * 127 / 128],
+                       rtol=0, atol=1e-15)
+    q = np.arange(256, dtype=np.uint8)
+    assert np.array_equal(orc.codes_from_angles(orc.angles_from_codes(q)), q)
+    assert orc.codes_from_angles(np.array([math.pi]))[0] == 0      # pi wraps to -pi
+    # a transform from codes is the transform of the decoded angles (zero code = identity)
+    x = np.random.default_rng(1).standard_normal((5, 16))
+    zero = np.full((1, 2, 4, 8), 128, dtype=np.uint8)
+    assert np.allclose(orc.forward(x, None, orc.angles_from_codes(zero)), x, rtol=0, atol=0)
+
+
+def test_permutation_pass():
+    """Identity permutation = forward; outputs are the forward coefficients
+    rearranged; the round trip is exact up to rounding; the variance order
+    leaves each class's coefficient variances non-increasing."""
+    from paper_2505_21728_amd import synth
+
+    ang = synth.angles(3, 2, 4).astype(np.float64)
+    x = synth.ar1_blocks(300, 4, seed=2).astype(np.float64)
+    cls = synth.classes(300, 3, seed=3)
+    ident = np.tile(np.arange(16), (3, 1))
+    y = orc.forward(x, cls, ang)
+    assert np.array_equal(orc.forward_permuted(x, cls, ang, ident), y)
+    perm = orc.variance_order(y, cls, 3)
+    for c in range(3):
+        assert sorted(perm[c]) == list(range(16))
+    yp = orc.forward_permuted(x, cls, ang, perm)
+    for b in range(300):
+        assert np.array_equal(yp[b], y[b, perm[cls[b]]])
+    for c in range(3):
+        var = np.mean(yp[cls == c] ** 2, axis=0)
+        assert np.all(np.diff(var) <= 1e-9 * var.max())
+    z = orc.inverse_permuted(yp, cls, ang, perm)
+    assert np.allclose(z, x, rtol=0, atol=1e-10)
