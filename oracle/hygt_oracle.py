@@ -432,6 +432,97 @@ def variance_order(y, cls, nclasses: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Integer arithmetic (Sec. IV, Fig. 6): integer blocks, multipliers from a
+# shared table of fixed-point cosines and sines indexed by the 8-bit code
+# ---------------------------------------------------------------------------
+
+INT_FRAC_BITS = 14
+
+
+def int_multipliers(codes) -> tuple[np.ndarray, np.ndarray]:
+    """Fixed-point (C, S) = round(2^14 cos, 2^14 sin) of each code's angle.
+
+    Fig. 6 converts each low-bit parameter to higher-precision multipliers
+    through a table of sines and cosines shared by all transforms, and the
+    text asks for well-defined integer arithmetic without giving the word
+    length or the rounding (parity unpinned for those choices). This reading
+    takes 14 fractional bits and rounds half to even in FP64.
+    """
+    th = angles_from_codes(codes)
+    scale = float(1 << INT_FRAC_BITS)
+    return (np.rint(scale * np.cos(th)).astype(np.int64),
+            np.rint(scale * np.sin(th)).astype(np.int64))
+
+
+def _int_rotate(xm, xn, c, s):
+    """One integer butterfly: eq. (7) with fixed-point multipliers, each
+    output rounded to the nearest integer (ties upwards) by an arithmetic
+    shift. All operands are int64, so nothing overflows."""
+    half = 1 << (INT_FRAC_BITS - 1)
+    ym = (c * xm + s * xn + half) >> INT_FRAC_BITS
+    yn = (c * xn - s * xm + half) >> INT_FRAC_BITS
+    return ym, yn
+
+
+def _check_int(x, cls, codes):
+    x = np.asarray(x)
+    if not np.issubdtype(x.dtype, np.integer):
+        raise TypeError("integer blocks expected")
+    codes = np.asarray(codes)
+    if codes.dtype != np.uint8 or codes.ndim != 4:
+        raise TypeError("codes must be uint8 [C, R, d, N/2]")
+    nclasses, rounds, d, half = codes.shape
+    if x.ndim != 2 or x.shape[1] != 2 * half or 1 << d != x.shape[1]:
+        raise ValueError("blocks do not match the codes")
+    cls = np.zeros(x.shape[0], np.int64) if cls is None else np.asarray(cls, np.int64)
+    if cls.size and (cls.min() < 0 or cls.max() >= nclasses):
+        raise ValueError("class out of range")
+    return x.astype(np.int64), cls, codes, rounds, d
+
+
+def forward_int(x, cls, codes) -> np.ndarray:
+    """Integer HyGT: R rounds of d passes in the order of eq. (5), each
+    butterfly an integer rotation with the multipliers of its code."""
+    y, cls, codes, rounds, d = _check_int(x, cls, codes)
+    c_tab, s_tab = int_multipliers(codes)
+    for r in range(rounds):
+        for k in range(d):
+            m, n = pair_indices(d, k)
+            c = c_tab[cls, r, k, :]
+            s = s_tab[cls, r, k, :]
+            y[:, m], y[:, n] = _int_rotate(y[:, m], y[:, n], c, s)
+    return y
+
+
+def inverse_int(y, cls, codes) -> np.ndarray:
+    """Integer inverse: the passes in reverse order with negated angles
+    (eq. (9)), i.e. multipliers (C, -S). Not an exact inverse of
+    forward_int(): each butterfly rounds."""
+    x, cls, codes, rounds, d = _check_int(y, cls, codes)
+    c_tab, s_tab = int_multipliers(codes)
+    for r in reversed(range(rounds)):
+        for k in reversed(range(d)):
+            m, n = pair_indices(d, k)
+            c = c_tab[cls, r, k, :]
+            s = s_tab[cls, r, k, :]
+            x[:, m], x[:, n] = _int_rotate(x[:, m], x[:, n], c, -s)
+    return x
+
+
+def int_error_bound(x_norm: float, n_elems: int, passes: int) -> float:
+    """Bound on ||forward_int(x) - forward(x, angles of the codes)||_2 for a
+    block of L2 norm x_norm. Per pass the rounding adds at most sqrt(N)/2
+    and the multiplier quantisation (each entry within 2^-15) at most
+    sqrt(2) 2^-15 times the current norm; the exact passes are orthogonal
+    and so carry the earlier error unchanged."""
+    delta = math.sqrt(2.0) * 2.0 ** -(INT_FRAC_BITS + 1)
+    e = 0.0
+    for _ in range(passes):
+        e += delta * (x_norm + e) + 0.5 * math.sqrt(n_elems)
+    return e
+
+
+# ---------------------------------------------------------------------------
 # Comparison metric
 # ---------------------------------------------------------------------------
 

@@ -549,3 +549,143 @@ def test_permutation_pass():
         assert np.all(np.diff(var) <= 1e-9 * var.max())
     z = orc.inverse_permuted(yp, cls, ang, perm)
     assert np.allclose(z, x, rtol=0, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Integer arithmetic (Fig. 6): fixed-point multipliers, rounded butterflies
+# ---------------------------------------------------------------------------
+
+def _int_golden():
+    with open(os.path.join(GOLDEN, "int_butterfly_n2_worked.json")) as f:
+        return json.load(f)
+
+
+def pin_int_golden(o):
+    g = _int_golden()
+    assert g["frac_bits"] == o.INT_FRAC_BITS
+    for case in g["cases"]:
+        codes = np.full((1, 1, 1, 1), case["code"], dtype=np.uint8)
+        c, s = o.int_multipliers(codes)
+        assert (int(c.ravel()[0]), int(s.ravel()[0])) == (case["C"], case["S"]), case["angle"]
+        x = np.array([case["x"]], dtype=np.int64)
+        y = o.forward_int(x, None, codes)
+        assert y.tolist() == [case["forward"]], case["angle"]
+        assert o.inverse_int(y, None, codes).tolist() == [case["inverse_of_forward"]], case["angle"]
+
+
+def pin_int_signed_permutations(o):
+    """Codes 0, 64, 128, 192 are the angles -pi, -pi/2, 0, pi/2, whose
+    multipliers are exact: every butterfly is then a signed swap, so the
+    integer transform equals the exact FP64 one and inverts exactly."""
+    rng = np.random.default_rng(41)
+    C, R, d = 3, 3, 4
+    codes = rng.choice(np.array([0, 64, 128, 192], dtype=np.uint8), size=(C, R, d, 8))
+    x = rng.integers(-300, 301, size=(200, 16))
+    cls = rng.integers(0, C, size=200)
+    y = o.forward_int(x, cls, codes)
+    ref = o.forward(x.astype(np.float64), cls, o.angles_from_codes(codes))
+    assert np.array_equal(y, np.rint(ref).astype(np.int64))
+    assert np.max(np.abs(ref - np.rint(ref))) < 1e-9
+    assert np.array_equal(o.inverse_int(y, cls, codes), x)
+
+
+def pin_int_error_bound_and_bias(o):
+    """Against the FP64 transform with the codes' exact angles: every block
+    within the bound of int_error_bound(); rounding to nearest leaves no
+    systematic offset (the mean error over many outputs stays near 0)."""
+    rng = np.random.default_rng(43)
+    C, R, d = 5, 4, 6
+    codes = rng.integers(0, 256, size=(C, R, d, 32)).astype(np.uint8)
+    x = rng.integers(-255, 256, size=(1500, 64))
+    cls = rng.integers(0, C, size=1500)
+    y = o.forward_int(x, cls, codes)
+    ref = o.forward(x.astype(np.float64), cls, o.angles_from_codes(codes))
+    err = np.linalg.norm(y - ref, axis=1)
+    norms = np.linalg.norm(x.astype(np.float64), axis=1)
+    bound = np.array([o.int_error_bound(nv, 64, R * d) for nv in norms])
+    assert np.all(err <= bound)
+    assert abs(float(np.mean(y - ref))) < 0.05
+    # the inverse undoes the forward up to the same kind of rounding error
+    back = o.inverse_int(y, cls, codes)
+    assert np.all(np.linalg.norm(back - x, axis=1) <= 2 * bound)
+
+
+def test_int_multiplier_table():
+    """All 256 entries: |C|, |S| <= 2^14, C^2 + S^2 within rounding of 2^28,
+    and 2^14 cos, 2^14 sin never within 1e-6 of a rounding tie, so every
+    correctly rounded FP64 cosine and sine gives this same table."""
+    codes = np.arange(256, dtype=np.uint8)
+    c, s = orc.int_multipliers(codes)
+    assert np.all(np.abs(c) <= 1 << 14) and np.all(np.abs(s) <= 1 << 14)
+    assert np.all(np.abs(c * c + s * s - (1 << 28)) <= 2 * (1 << 14))
+    th = orc.angles_from_codes(codes)
+    for v in (16384.0 * np.cos(th), 16384.0 * np.sin(th)):
+        frac = np.abs(v - np.floor(v) - 0.5)
+        assert np.all(frac > 1e-6)
+    assert (c[128], s[128]) == (16384, 0) and (c[192], s[192]) == (0, 16384)
+    assert (c[0], s[0]) == (-16384, 0) and (c[64], s[64]) == (0, -16384)
+
+
+INT_PINS = [pin_int_golden, pin_int_signed_permutations, pin_int_error_bound_and_bias]
+
+
+@pytest.mark.parametrize("pin", INT_PINS, ids=lambda p: p.__name__)
+def test_int_pins(pin):
+    pin(orc)
+
+
+def _mutant_int(half=True, trunc_div=False, s_sign_yn=-1, inv_neg=True):
+    frac = orc.INT_FRAC_BITS
+
+    def rot(xm, xn, c, s):
+        h = (1 << (frac - 1)) if half else 0
+        a = c * xm + s * xn + h
+        b = c * xn + s_sign_yn * s * xm + h
+        if trunc_div:
+            return (np.trunc(a / (1 << frac)).astype(np.int64),
+                    np.trunc(b / (1 << frac)).astype(np.int64))
+        return a >> frac, b >> frac
+
+    def fwd(x, cls, codes):
+        y, cls, codes, rounds, d = orc._check_int(x, cls, codes)
+        ct, st = orc.int_multipliers(codes)
+        for r in range(rounds):
+            for k in range(d):
+                m, n = orc.pair_indices(d, k)
+                y[:, m], y[:, n] = rot(y[:, m], y[:, n], ct[cls, r, k], st[cls, r, k])
+        return y
+
+    def inv(y, cls, codes):
+        x, cls, codes, rounds, d = orc._check_int(y, cls, codes)
+        ct, st = orc.int_multipliers(codes)
+        for r in reversed(range(rounds)):
+            for k in reversed(range(d)):
+                m, n = orc.pair_indices(d, k)
+                s = -st[cls, r, k] if inv_neg else st[cls, r, k]
+                x[:, m], x[:, n] = rot(x[:, m], x[:, n], ct[cls, r, k], s)
+        return x
+
+    return _Mutant(forward_int=fwd, inverse_int=inv)
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("floor_without_half", {"half": False}),
+    ("truncate_toward_zero", {"trunc_div": True}),
+    ("sine_sign_in_second_output", {"s_sign_yn": 1}),
+    ("inverse_without_negated_angle", {"inv_neg": False}),
+])
+def test_int_pins_catch_mutant(name, kw):
+    mutant = _mutant_int(**kw)
+    failures = 0
+    for pin in INT_PINS:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"no pin caught mutant {name}"
+
+
+def test_int_unmutated_harness_passes():
+    m = _mutant_int()
+    for pin in INT_PINS:
+        pin(m)
