@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -142,6 +143,57 @@ def _klt_comparison(torch, hygt, at, cs, xs, steps):
             "flops_per_launch": NBLOCKS * 2 * N * N,
             "matrix_bytes_bf16": C * N * N * 2,
             "hygt_angle_bytes_f32": C * ROUNDS * LOG2N * (N // 2) * 4}
+
+
+def _variants(torch, hygt, at, cs, xs, steps):
+    """The paper's variants on the same blocks and classes, forward then
+    inverse: the permutation pass of Fig. 4 (per-class variance order of the
+    first batch) and the integer transform of Fig. 6 (int32 blocks with the
+    same integer values, angles rounded to 8-bit codes)."""
+    dev = xs[0].device
+    plans = [hygt.Plan(at, c) for c in cs]
+    y = torch.empty_like(xs[0])
+    z = torch.empty_like(xs[0])
+    # variance order per class, from the first batch's coefficients
+    plans[0].forward(xs[0], out=y)
+    var = torch.zeros(NCLASSES, N, dtype=torch.float64, device=dev)
+    var.index_add_(0, cs[0].long(), (y.double() ** 2))
+    perm = torch.argsort(-var, dim=1, stable=True).to(torch.int32).contiguous()
+    codes = torch.remainder(torch.round(at.double() * (128.0 / math.pi)) + 128, 256)
+    codes = codes.to(torch.uint8).contiguous()
+    iplans = [hygt.Plan(codes, c, integer=True) for c in cs]
+    xi = [x.to(torch.int32) for x in xs]
+    yi = torch.empty_like(xi[0])
+    zi = torch.empty_like(xi[0])
+
+    def timed(run_fwd, run_inv):
+        for k in range(3):
+            run_fwd(k)
+            run_inv(k)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
+        torch.cuda.synchronize()
+        for i in range(steps):
+            ev[4 * i].record(stream)
+            run_fwd(i)
+            ev[4 * i + 1].record(stream)
+            ev[4 * i + 2].record(stream)
+            run_inv(i)
+            ev[4 * i + 3].record(stream)
+        torch.cuda.synchronize()
+        fwd = sum(ev[4 * i].elapsed_time(ev[4 * i + 1]) for i in range(steps)) / steps
+        inv = sum(ev[4 * i + 2].elapsed_time(ev[4 * i + 3]) for i in range(steps)) / steps
+        return {"fwd_ms": fwd, "inv_ms": inv,
+                "fwd_gbps": NBLOCKS * BYTES_PER_BLOCK / (fwd / 1e3) / 1e9}
+
+    perm_t = timed(
+        lambda k: plans[k % RING].apply_permuted(xs[k % RING], hygt.HYGT_FORWARD, perm, out=y),
+        lambda k: plans[k % RING].apply_permuted(y, hygt.HYGT_INVERSE, perm, out=z))
+    int_t = timed(lambda k: iplans[k % RING].forward(xi[k % RING], out=yi),
+                  lambda k: iplans[k % RING].inverse(yi, out=zi))
+    return {"permutation_pass": dict(kernel="rotate_perm_kernel<6,*>", **perm_t),
+            "integer": dict(kernel="rotate_int_kernel<6,*> (int32, 14-bit multipliers)",
+                            **int_t)}
 
 
 def _grad_step(torch, hygt, at, cs, xs, steps):
@@ -370,6 +422,7 @@ def main():
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
     klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
+    variants = _variants(torch, hygt, at, cs, xs, args.steps)
     grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
     mixed = _mixed_workload(torch, hygt, args.steps)
     served = _serve_workload(torch)
@@ -406,6 +459,7 @@ def main():
                      "bytes_per_launch": launch_bytes,
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
         "klt_dense": klt,
+        "variants": variants,
         "grad_step": grad,
         "mixed": mixed,
         "serve": served,

@@ -150,6 +150,36 @@ int hygt_apply_perm(const float* x, float* y, int64_t nblocks, int log2n, int ro
                     int nclasses, int direction, const int32_t* perm,
                     const void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Largest block length (log2) of the integer transform. */
+#define HYGT_INT_MAX_LOG2N 6
+
+/* Plan for the integer transform (Sec. IV, Fig. 6: one byte per parameter,
+ * converted through a shared table of sines and cosines into higher
+ * precision multipliers; integer arithmetic as video coding standards need).
+ * codes: uint8 [nclasses][rounds][log2n][N/2] in the layout of hygt_plan's
+ * angles, code q meaning the angle (q - 128) pi / 128. Each pair gets the
+ * fixed-point multipliers C = round(2^14 cos), S = round(2^14 sin) (FP64,
+ * ties to even). 2 <= log2n <= HYGT_INT_MAX_LOG2N. The workspace is then for
+ * hygt_apply_int() only. Other arguments and errors as hygt_plan(). */
+int hygt_plan_int(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
+                  const uint8_t* codes, int nclasses, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+
+/* The integer transform of int32 blocks x[nblocks][N] into y (same layout;
+ * y == x allowed, other overlaps rejected; 16-byte aligned). Every butterfly
+ * of eq. (7) computes
+ *   y_m = (C x_m + S x_n + 2^13) >> 14,   y_n = (C x_n - S x_m + 2^13) >> 14
+ * (arithmetic shift: rounding to nearest, ties upwards). The inverse runs the
+ * passes in reverse order with multipliers (C, -S) (eq. (9)); it undoes the
+ * forward transform up to the rounding of each butterfly, not exactly.
+ * Results are exact (bit-identical to this definition in unbounded integers)
+ * for blocks of L2 norm at most 2^15, e.g. residuals within +-4095 for
+ * N = 64; beyond that they are deterministic but unspecified. The workspace
+ * must come from hygt_plan_int() with the same sizes. */
+int hygt_apply_int(const int32_t* x, int32_t* y, int64_t nblocks, int log2n, int rounds,
+                   int nclasses, int direction, const void* workspace,
+                   size_t workspace_bytes, hipStream_t stream);
+
 /* hygt_plan() followed by hygt_apply(HYGT_FORWARD): y[b] = T_{cls[b]} x[b]. */
 int hygt_forward(const float* x, float* y, const int32_t* cls, int64_t nblocks,
                  int log2n, int rounds, const float* angles, int nclasses,

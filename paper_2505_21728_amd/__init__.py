@@ -16,8 +16,8 @@ from __future__ import annotations
 import math
 
 from . import _abi
-from ._abi import (HYGT_BACKWARD_MAX_LOG2N, HYGT_DENSE_LOG2N, HYGT_FORWARD, HYGT_INVERSE,
-                   HYGT_MAX_BLOCKS, HYGT_MAX_CLASSES, HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS,
+from ._abi import (HYGT_BACKWARD_MAX_LOG2N, HYGT_DENSE_LOG2N, HYGT_FORWARD, HYGT_INT_MAX_LOG2N,
+                   HYGT_INVERSE, HYGT_MAX_BLOCKS, HYGT_MAX_CLASSES, HYGT_MAX_LOG2N, HYGT_MAX_ROUNDS,
                    HygtError)
 
 __all__ = ["Plan", "MixedBatch", "forward", "inverse", "transform", "workspace_bytes",
@@ -53,16 +53,20 @@ class Plan:
     """
 
     def __init__(self, angles, cls=None, nblocks: int | None = None, stream=None,
-                 workspace=None):
+                 workspace=None, integer: bool = False):
         torch = _torch()
         _require(isinstance(angles, torch.Tensor), "angles must be a torch.Tensor", TypeError)
         _require(angles.is_cuda, "angles must be on a HIP device")
         _require(angles.dtype in (torch.float32, torch.uint8),
                  "angles must be float32 radians or uint8 codes", TypeError)
+        _require(not integer or angles.dtype == torch.uint8,
+                 "the integer transform takes uint8 codes", TypeError)
         _require(angles.dim() == 4, "angles must be [nclasses, rounds, log2n, N/2]")
         _require(angles.is_contiguous(), "angles must be contiguous")
         nclasses, rounds, log2n, half = (int(s) for s in angles.shape)
         _require(1 <= log2n <= HYGT_MAX_LOG2N, f"log2n must be in [1, {HYGT_MAX_LOG2N}]")
+        _require(not integer or 2 <= log2n <= HYGT_INT_MAX_LOG2N,
+                 f"the integer transform takes 2 <= log2n <= {HYGT_INT_MAX_LOG2N}")
         _require(half == 1 << (log2n - 1), "angles last dimension must be N/2 = 2^(log2n-1)")
         _require(1 <= rounds <= HYGT_MAX_ROUNDS, f"rounds must be in [1, {HYGT_MAX_ROUNDS}]")
         _require(1 <= nclasses <= HYGT_MAX_CLASSES,
@@ -94,7 +98,11 @@ class Plan:
         _require(workspace.data_ptr() % 256 == 0, "workspace must be 256-byte aligned")
         self.workspace = workspace
         self._stream = stream
-        plan_fn = _abi.hygt_plan_codes if angles.dtype == torch.uint8 else _abi.hygt_plan
+        self.integer = bool(integer)
+        if self.integer:
+            plan_fn = _abi.hygt_plan_int
+        else:
+            plan_fn = _abi.hygt_plan_codes if angles.dtype == torch.uint8 else _abi.hygt_plan
         with torch.cuda.device(self.device):
             st = plan_fn(0 if cls is None else cls.data_ptr(), self.nblocks, log2n,
                          rounds, angles.data_ptr(), nclasses, workspace.data_ptr(),
@@ -105,7 +113,8 @@ class Plan:
         torch = _torch()
         _require(isinstance(x, torch.Tensor), "x must be a torch.Tensor", TypeError)
         _require(x.device == self.device, "x must be on the plan's device")
-        _require(x.dtype == torch.float32, "x must be float32", TypeError)
+        want = torch.int32 if self.integer else torch.float32
+        _require(x.dtype == want, f"x must be {want}", TypeError)
         _require(x.dim() == 2 and tuple(x.shape) == (self.nblocks, self.n),
                  f"x must be [{self.nblocks}, {self.n}]")
         _require(x.is_contiguous(), "x must be contiguous")
@@ -121,11 +130,12 @@ class Plan:
         else:
             self._check_x(out)
         s = stream if stream is not None else self._stream
+        fn = _abi.hygt_apply_int if self.integer else _abi.hygt_apply
         with torch.cuda.device(self.device):
-            st = _abi.hygt_apply(x.data_ptr(), out.data_ptr(), self.nblocks, self.log2n,
-                                 self.rounds, self.nclasses, direction,
-                                 self.workspace.data_ptr(), self.ws_bytes, _stream_handle(s))
-        _abi._check(st, "hygt_apply")
+            st = fn(x.data_ptr(), out.data_ptr(), self.nblocks, self.log2n, self.rounds,
+                    self.nclasses, direction, self.workspace.data_ptr(), self.ws_bytes,
+                    _stream_handle(s))
+        _abi._check(st, "hygt_apply_int" if self.integer else "hygt_apply")
         return out
 
     def forward(self, x, out=None, stream=None):
@@ -140,6 +150,7 @@ class Plan:
         """The transform with the permutation pass of Fig. 4: perm [C, N]
         int32 rows give, for each output position, its source coefficient
         (forward); the inverse undoes it first. N <= 64."""
+        _require(not self.integer, "not available for the integer transform")
         torch = _torch()
         self._check_x(x)
         _require(isinstance(perm, torch.Tensor) and perm.dtype == torch.int32 and
@@ -161,6 +172,7 @@ class Plan:
     def dense(self, x, mats, out=None):
         """y[b] = M_{cls[b]} x[b] with BF16 matrices mats [C, N, N] on the
         matrix cores (the dense transform of eq. (3)); N = 64 only."""
+        _require(not self.integer, "not available for the integer transform")
         torch = _torch()
         self._check_x(x)
         _require(self.log2n == HYGT_DENSE_LOG2N, "dense transform needs N = 64")
@@ -187,6 +199,7 @@ class Plan:
         gy = dL/dy, returns (gx, gangles) with gx = dL/dx = T^T gy and
         gangles = dL/dangles summed over each class's blocks. `angles` must be
         the tensor this plan was built from. N <= 64."""
+        _require(not self.integer, "not available for the integer transform")
         torch = _torch()
         self._check_x(y)
         self._check_x(gy)

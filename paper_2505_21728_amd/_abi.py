@@ -29,6 +29,8 @@ HYGT_MAX_CLASSES = 4096
 HYGT_MAX_BLOCKS = 2147483647
 HYGT_DENSE_LOG2N = 6
 HYGT_BACKWARD_MAX_LOG2N = 6
+HYGT_PERM_MAX_LOG2N = 6
+HYGT_INT_MAX_LOG2N = 6
 
 HYGT_MAX_SEGMENTS = 4
 
@@ -49,6 +51,10 @@ _SIGNATURES = {
     "hygt_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int, _c.c_int, _c.c_int]),
     "hygt_plan": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int, _c.c_void_p,
                              _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_plan_int": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int, _c.c_void_p,
+                                 _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_apply_int": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
+                                  _c.c_int, _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_apply_perm": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int, _c.c_int,
                                    _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_size_t,
                                    _c.c_void_p]),
@@ -138,6 +144,18 @@ def hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr, ws_
               stream) -> int:
     return load().hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
                             ws_bytes, stream)
+
+
+def hygt_plan_int(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr, ws_bytes,
+                  stream) -> int:
+    return load().hygt_plan_int(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr,
+                                ws_bytes, stream)
+
+
+def hygt_apply_int(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr, ws_bytes,
+                   stream) -> int:
+    return load().hygt_apply_int(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction,
+                                 ws_ptr, ws_bytes, stream)
 
 
 def hygt_apply_perm(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, perm_ptr, ws_ptr,

@@ -38,7 +38,8 @@ bool overlap_ok(const float* x, const float* y, int64_t nblocks, int log2n) {
 }
 
 int plan_any(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const float* angles,
-             const uint8_t* codes, int nclasses, void* ws, size_t ws_bytes, hipStream_t stream) {
+             const uint8_t* codes, int integer, int nclasses, void* ws, size_t ws_bytes,
+             hipStream_t stream) {
     if (!sizes_ok(nblocks, log2n, rounds, nclasses)) return HYGT_EINVAL;
     const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
     if (int s = check_workspace(ws, ws_bytes, l)) return s;
@@ -47,15 +48,16 @@ int plan_any(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const f
     if (angles != nullptr && !aligned(angles, 4)) return HYGT_EINVAL;
     if (cls == nullptr && nclasses != 1) return HYGT_EINVAL;
     if (cls != nullptr && !aligned(cls, 4)) return HYGT_EINVAL;
-    const hipError_t e = hygt::launch_plan(cls, nblocks, log2n, rounds, angles, codes, nclasses,
-                                           l, hygt::ws_ptrs(ws, l), stream);
+    const hipError_t e = hygt::launch_plan(cls, nblocks, log2n, rounds, angles, codes, integer,
+                                           nclasses, l, hygt::ws_ptrs(ws, l), stream);
     return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 
 int plan_impl(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const float* angles,
               int nclasses, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (nblocks > 0 && angles == nullptr) return HYGT_EINVAL;
-    return plan_any(cls, nblocks, log2n, rounds, angles, nullptr, nclasses, ws, ws_bytes, stream);
+    return plan_any(cls, nblocks, log2n, rounds, angles, nullptr, 0, nclasses, ws, ws_bytes,
+                    stream);
 }
 
 int apply_impl(const float* x, float* y, int64_t nblocks, int log2n, int rounds, int nclasses,
@@ -306,8 +308,36 @@ int hygt_plan_codes(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
                     const uint8_t* codes, int nclasses, void* workspace, size_t workspace_bytes,
                     hipStream_t stream) {
     if (nblocks > 0 && codes == nullptr) return HYGT_EINVAL;
-    return plan_any(cls, nblocks, log2n, rounds, nullptr, codes, nclasses, workspace,
+    return plan_any(cls, nblocks, log2n, rounds, nullptr, codes, 0, nclasses, workspace,
                     workspace_bytes, stream);
+}
+
+int hygt_plan_int(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
+                  const uint8_t* codes, int nclasses, void* workspace, size_t workspace_bytes,
+                  hipStream_t stream) {
+    if (log2n < 2 || log2n > HYGT_INT_MAX_LOG2N) return HYGT_EINVAL;
+    if (nblocks > 0 && codes == nullptr) return HYGT_EINVAL;
+    return plan_any(cls, nblocks, log2n, rounds, nullptr, codes, 1, nclasses, workspace,
+                    workspace_bytes, stream);
+}
+
+int hygt_apply_int(const int32_t* x, int32_t* y, int64_t nblocks, int log2n, int rounds,
+                   int nclasses, int direction, const void* workspace, size_t workspace_bytes,
+                   hipStream_t stream) {
+    if (!sizes_ok(nblocks, log2n, rounds, nclasses)) return HYGT_EINVAL;
+    if (log2n < 2 || log2n > HYGT_INT_MAX_LOG2N) return HYGT_EINVAL;
+    if (direction != HYGT_FORWARD && direction != HYGT_INVERSE) return HYGT_EINVAL;
+    const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
+    if (int s = check_workspace(workspace, workspace_bytes, l)) return s;
+    if (nblocks == 0) return HYGT_OK;
+    if (x == nullptr || y == nullptr) return HYGT_EINVAL;
+    if (!aligned(x, 16) || !aligned(y, 16)) return HYGT_EINVAL;
+    const float* xf = reinterpret_cast<const float*>(x);
+    if (!overlap_ok(xf, reinterpret_cast<const float*>(y), nblocks, log2n)) return HYGT_EINVAL;
+    const hipError_t e = hygt::launch_rotate_int(
+        x, y, nblocks, log2n, rounds, nclasses, direction, l,
+        hygt::ws_ptrs(const_cast<void*>(workspace), l), stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 
 size_t hygt_mixed_workspace_bytes(const hygt_segment* segs, int nseg) {

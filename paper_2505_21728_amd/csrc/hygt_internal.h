@@ -123,8 +123,19 @@ inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
 // hipError_t of its launches.
 // Exactly one of angles (FP32 radians) and codes (8-bit codes) is non-NULL.
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
-                       const float* angles, const uint8_t* codes, int nclasses,
+                       const float* angles, const uint8_t* codes, int integer, int nclasses,
                        const WsLayout& l, const WsPtrs& p, hipStream_t stream);
+
+// Integer arithmetic: multipliers with kIntFracBits fractional bits, outputs
+// rounded by adding half a unit and shifting right (floor).
+constexpr int kIntFracBits = 14;
+constexpr double kIntOne = 16384.0;  // 2^kIntFracBits
+
+// The integer transform (hygt_rotate.hip) on int32 blocks, 4 <= N <= 64,
+// with tables built by launch_plan(integer = 1).
+hipError_t launch_rotate_int(const int32_t* x, int32_t* y, int64_t nblocks, int log2n,
+                             int rounds, int nclasses, int direction, const WsLayout& l,
+                             const WsPtrs& p, hipStream_t stream);
 
 hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                          int nclasses, int direction, const WsLayout& l, const WsPtrs& p,

@@ -199,6 +199,35 @@ __device__ void build_table(TableShared& sh, int dir, int c, const float* __rest
     if (tid == 0) modes[table] = neg ? 1 : 0;
 }
 
+// Integer tables (Fig. 6 with integer arithmetic): for every pair, in the
+// passes' application order, the fixed-point multipliers
+// (C, S) = (round(2^14 cos th), round(2^14 sin th)) of its code's angle th
+// (negated for the inverse, eq. (9)), stored as two int32 in the slots of the
+// lifting pair. No sign bookkeeping: the signs stay +1.
+__device__ void build_table_int(int dir, int c, const uint8_t* __restrict__ codes, int log2n,
+                                int rounds, int nclasses, float* __restrict__ coef,
+                                float* __restrict__ signs, int32_t* __restrict__ modes) {
+    const int n = 1 << log2n;
+    const int half = n >> 1;
+    const int passes = rounds * log2n;
+    const size_t table = static_cast<size_t>(dir) * nclasses + c;
+    int32_t* cbase = reinterpret_cast<int32_t*>(coef) + table * passes * n;
+    for (int e = threadIdx.x; e < passes * half; e += blockDim.x) {
+        const int p = e / half;
+        const int j = e % half;
+        const int kk = p % log2n, rr = p / log2n;
+        const int k = dir ? log2n - 1 - kk : kk;
+        const int r = dir ? rounds - 1 - rr : rr;
+        const size_t ai = ((static_cast<size_t>(c) * rounds + r) * log2n + k) * half + j;
+        double th = code_angle(codes[ai]);
+        if (dir) th = -th;
+        cbase[static_cast<size_t>(p) * n + 2 * j + 0] = static_cast<int32_t>(rint(kIntOne * cos(th)));
+        cbase[static_cast<size_t>(p) * n + 2 * j + 1] = static_cast<int32_t>(rint(kIntOne * sin(th)));
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) signs[table * n + i] = 1.0f;
+    if (threadIdx.x == 0) modes[table] = 0;
+}
+
 // Tiles of a class of `count` blocks: whole tiles of 64, rounded up to a
 // multiple of the tiles a rotation wavefront takes at once.
 __device__ __forceinline__ int class_tiles(int count) {
@@ -286,11 +315,16 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
     int32_t* __restrict__ tile_class, int32_t* __restrict__ perm,
     const float* __restrict__ angles, const uint8_t* __restrict__ codes, int log2n, int rounds,
-    int32_t* __restrict__ modes,
+    int integer, int32_t* __restrict__ modes,
     float* __restrict__ coef, float* __restrict__ signs) {
     extern __shared__ __align__(16) int place_dyn[];
     if (blockIdx.x < 2 * nclasses) {
         const int wg = static_cast<int>(blockIdx.x);
+        if (integer) {
+            build_table_int(wg / nclasses, wg % nclasses, codes, log2n, rounds, nclasses, coef,
+                            signs, modes);
+            return;
+        }
         build_table(*reinterpret_cast<TableShared*>(place_dyn), wg / nclasses, wg % nclasses,
                     angles, codes, log2n, rounds, nclasses, coef, signs, modes);
         return;
@@ -409,7 +443,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
 }  // namespace
 
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
-                       const float* angles, const uint8_t* codes, int nclasses,
+                       const float* angles, const uint8_t* codes, int integer, int nclasses,
                        const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
     hipLaunchKernelGGL(plan_count_kernel, dim3(static_cast<unsigned>(l.nchunks)),
                        dim3(kPlanThreads), 0, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
@@ -426,7 +460,7 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
     hipLaunchKernelGGL(plan_place_kernel, dim3(static_cast<unsigned>(2 * nclasses + l.nchunks)),
                        dim3(kPlanThreads), lds, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
                        l.max_tiles, p.counts, p.tile_class, p.perm, angles, codes, log2n,
-                       rounds, p.modes, p.coef, p.signs);
+                       rounds, integer, p.modes, p.coef, p.signs);
     return hipGetLastError();
 }
 

@@ -105,6 +105,58 @@ __device__ __forceinline__ void run_passes(float (&v)[T][1 << D], ctab_f tbl, ct
     }
 }
 
+// Integer arithmetic (Fig. 6): the registers hold int32 values (as bit
+// patterns), and pair j's multipliers (C, S) come from the integer table.
+// y_m = (C x_m + S x_n + 2^13) >> 14, y_n = (C x_n - S x_m + 2^13) >> 14, with
+// 24-bit multiplies (v_mad_i32_i24, full rate): exact while every value stays
+// within +-2^23 and every sum within int32, which holds for blocks of L2 norm
+// up to 2^15.
+// p * q + r with p, q taken as signed 24-bit integers (one full-rate
+// v_mad_i32_i24; left to itself the compiler splits such sums into
+// multiplies and a three-input add, two instructions more per pair).
+__device__ __forceinline__ int mad24(int p, int q, int r) {
+    int out;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(out) : "s"(p), "v"(q), "v"(r));
+    return out;
+}
+
+template <int D, int K, int T>
+__device__ __forceinline__ void pass_int(float (&v)[T][1 << D], ctab_i cp, int half) {
+    StaticFor<0, (1 << D) / 2>::run([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        constexpr int m = ins0(j, K);
+        constexpr int n = m + (1 << K);
+        const int c = cp[2 * j];
+        const int s = cp[2 * j + 1];
+        const int ns = -s;
+        StaticFor<0, T>::run([&](auto uu) {
+            constexpr int u = decltype(uu)::value;
+            const int a = __float_as_int(v[u][m]);
+            const int b = __float_as_int(v[u][n]);
+            const int ym = mad24(c, a, mad24(s, b, half)) >> kIntFracBits;
+            const int yn = mad24(c, b, mad24(ns, a, half)) >> kIntFracBits;
+            v[u][m] = __int_as_float(ym);
+            v[u][n] = __int_as_float(yn);
+        });
+    });
+}
+
+template <int D, int DIR, int T>
+__device__ __forceinline__ void run_passes_int(float (&v)[T][1 << D], ctab_i tbl, int rounds) {
+    constexpr int N = 1 << D;
+    // the rounding constant, once in a VGPR (an instruction may read only
+    // one scalar operand, and the multiplier is that one)
+    int half = 1 << (kIntFracBits - 1);
+    asm volatile("" : "+v"(half));
+    for (int r = 0; r < rounds; ++r) {
+        StaticFor<0, D>::run([&](auto kk) {
+            constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
+            pass_int<D, K, T>(v, tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N,
+                              half);
+        });
+    }
+}
+
 // N >= 128: a pass along bit K >= 6 pairs value i of wavefront q (element
 // 64q + i, bit K - 6 of q clear) with value i of wavefront q | 2^(K-6). The
 // two swap their values through LDS, 16 per lane at a time, and each
@@ -250,7 +302,7 @@ __device__ __forceinline__ void unpermute_row(float* v, float4* R, ctab_i perm, 
 // completed, and no other wavefront touches it, so the restrict qualifiers
 // (which let the per-tile class loads stay scalar) hold for every pair of
 // accesses that the compiler could reorder.
-template <int D, int DIR, int RT, bool PERM = false>
+template <int D, int DIR, int RT, bool PERM = false, bool INTG = false>
 __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* __restrict__ y,
                                             int64_t nblocks, int rounds, int nclasses,
                                             int64_t t0, int c, int q,
@@ -303,6 +355,9 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
         // The partners' last reads of this wavefront's exchange area come
         // before the stores below reuse it for staging.
         __syncthreads();
+    } else if constexpr (INTG) {
+        run_passes_int<D, DIR, T>(
+            v, as_ctab(reinterpret_cast<const int32_t*>(coef)) + table * passes * N, rounds);
     } else {
         run_passes<D, DIR, RT, T>(v, as_ctab(coef) + table * passes * N,
                                   as_ctab(signs) + table * N, as_ctab(modes)[table], rounds);
@@ -375,6 +430,26 @@ __global__ __launch_bounds__(64 * kWaves) void rotate_perm_kernel(
     if (c < 0) return;
     rotate_tile<D, DIR, 0, true>(x, y, nblocks, rounds, nclasses, t0, c, 0, perm, modes, coef,
                                  signs, lds[wv], lds[wv], lane, as_ctab(outperm));
+}
+
+// Integer blocks, 4 <= N <= 64: as rotate_kernel with the integer passes;
+// loads, LDS staging and stores move the int32 bit patterns unchanged.
+template <int D, int DIR>
+__global__ __launch_bounds__(64 * kWaves) void rotate_int_kernel(
+    const float* __restrict__ x, float* __restrict__ y, int64_t nblocks, int rounds,
+    int nclasses, int64_t max_tiles, const int32_t* __restrict__ tile_class,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ modes,
+    const float* __restrict__ coef, const float* __restrict__ signs) {
+    using G = TileGeo<D>;
+    __shared__ float4 lds[kWaves][kTile * G::CHP];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    if (t0 >= max_tiles) return;
+    const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
+    if (c < 0) return;
+    rotate_tile<D, DIR, 0, false, true>(x, y, nblocks, rounds, nclasses, t0, c, 0, perm, modes,
+                                        coef, signs, lds[wv], lds[wv], lane);
 }
 
 // N == 2: one 8-byte block per lane, read and written directly.
@@ -641,6 +716,40 @@ hipError_t launch_perm_dir(const float* x, float* y, int64_t nblocks, int log2n,
     }
 }
 }  // namespace
+
+namespace {
+template <int D, int DIR>
+hipError_t launch_int_one(const int32_t* x, int32_t* y, int64_t nblocks, int rounds,
+                          int nclasses, const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
+    const int64_t groups = (l.max_tiles + kWaves - 1) / kWaves;
+    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    hipLaunchKernelGGL((rotate_int_kernel<D, DIR>), grid, dim3(64 * kWaves), 0, stream,
+                       reinterpret_cast<const float*>(x), reinterpret_cast<float*>(y), nblocks,
+                       rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes, p.coef,
+                       p.signs);
+    return hipGetLastError();
+}
+
+template <int DIR>
+hipError_t launch_int_dir(const int32_t* x, int32_t* y, int64_t nblocks, int log2n, int rounds,
+                          int nclasses, const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
+    switch (log2n) {
+        case 2: return launch_int_one<2, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        case 3: return launch_int_one<3, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        case 4: return launch_int_one<4, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        case 5: return launch_int_one<5, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        case 6: return launch_int_one<6, DIR>(x, y, nblocks, rounds, nclasses, l, p, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_rotate_int(const int32_t* x, int32_t* y, int64_t nblocks, int log2n,
+                             int rounds, int nclasses, int direction, const WsLayout& l,
+                             const WsPtrs& p, hipStream_t stream) {
+    if (direction == 0) return launch_int_dir<0>(x, y, nblocks, log2n, rounds, nclasses, l, p, stream);
+    return launch_int_dir<1>(x, y, nblocks, log2n, rounds, nclasses, l, p, stream);
+}
 
 hipError_t launch_rotate_perm(const float* x, float* y, int64_t nblocks, int log2n, int rounds,
                               int nclasses, int direction, const int32_t* outperm,

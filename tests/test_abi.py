@@ -43,6 +43,15 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, name)
 
 
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"^#define\s+(HYGT_\w+)\s+(-?\d+)\s*$", text, re.M))
+    assert defines, "no numeric #define found"
+    for name, value in defines.items():
+        assert hasattr(_abi, name), name
+        assert getattr(_abi, name) == int(value), name
+
+
 def test_strerror():
     for st in (0, -1, -2, -3, -4, -5):
         assert _abi.strerror(st)
@@ -141,6 +150,26 @@ def test_plan_codes_rejects():
     assert pc(FAKE, 100, 9, 2, FAKE, 3, FAKE, need, 0) == _abi.HYGT_EINVAL     # log2n
     assert pc(FAKE, 100, 4, 2, FAKE, 3, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
     assert pc(FAKE + 1, 0, 4, 2, FAKE + 1, 3, FAKE, need, 0) == _abi.HYGT_OK    # no-op
+
+
+def test_int_rejects():
+    need = _abi.hygt_workspace_bytes(100, 4, 2, 3)
+    pi, ai = _abi.hygt_plan_int, _abi.hygt_apply_int
+    x, y = FAKE, FAKE * 4
+    need1 = _abi.hygt_workspace_bytes(100, 1, 2, 3)
+    need7 = _abi.hygt_workspace_bytes(100, 7, 2, 3)
+    assert pi(FAKE, 100, 1, 2, FAKE, 3, FAKE, need1, 0) == _abi.HYGT_EINVAL      # N == 2
+    assert pi(FAKE, 100, 7, 2, FAKE, 3, FAKE, need7, 0) == _abi.HYGT_EINVAL      # N > 64
+    assert pi(FAKE, 100, 4, 2, 0, 3, FAKE, need, 0) == _abi.HYGT_EINVAL         # codes NULL
+    assert pi(FAKE, 100, 4, 2, FAKE, 3, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert pi(0, 0, 4, 2, 0, 3, FAKE, need, 0) == _abi.HYGT_OK                   # no-op
+    assert ai(x, y, 100, 7, 2, 3, 0, FAKE, need7, 0) == _abi.HYGT_EINVAL         # N > 64
+    assert ai(x, y, 100, 4, 2, 3, 5, FAKE, need, 0) == _abi.HYGT_EINVAL          # direction
+    assert ai(0, y, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL          # x NULL
+    assert ai(x + 8, y, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL      # misaligned
+    assert ai(x, x + 64, 100, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_EINVAL     # overlap
+    assert ai(x, y, 100, 4, 2, 3, 0, FAKE, need - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert ai(0, 0, 0, 4, 2, 3, 0, FAKE, need, 0) == _abi.HYGT_OK                # no-op
 
 
 def test_dense_rejects():

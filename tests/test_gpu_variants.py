@@ -149,3 +149,72 @@ def test_permutation_empty_and_ragged():
         y = plan.apply_permuted(_to(x, dev), hygt.HYGT_FORWARD, perm).cpu().numpy()
         if nblocks:
             _close(y, orc.forward_permuted(x, cls, ang, perm.cpu().numpy()), "ragged")
+
+
+# ---------------------------------------------------------------------------
+# Integer arithmetic: bit-exact against the oracle's unbounded integers
+# ---------------------------------------------------------------------------
+
+def _int_case(nblocks, d, rounds, C, seed, lim):
+    rng = np.random.default_rng(seed)
+    codes = rng.integers(0, 256, size=(C, rounds, d, 1 << (d - 1))).astype(np.uint8)
+    x = rng.integers(-lim, lim + 1, size=(nblocks, 1 << d)).astype(np.int32)
+    cls = rng.integers(0, C, size=nblocks).astype(np.int32)
+    return codes, x, cls
+
+
+@pytest.mark.parametrize("d,rounds,nblocks", [(2, 2, 257), (3, 3, 1000), (4, 4, 3001),
+                                              (5, 2, 2049), (6, 4, 4100), (6, 9, 700)])
+def test_integer_transform_bit_exact(d, rounds, nblocks):
+    import paper_2505_21728_amd as hygt
+    dev = _dev()
+    C = 6
+    _say(f"int d={d} R={rounds} B={nblocks}")
+    # residuals up to the documented limit: L2 norm <= 2^15 per block
+    lim = int((1 << 15) / np.sqrt(1 << d))
+    codes, x, cls = _int_case(nblocks, d, rounds, C, 500 + d + rounds, lim)
+    assert np.max(np.linalg.norm(x.astype(np.float64), axis=1)) <= 1 << 15
+    plan = hygt.Plan(_to(codes, dev), _to(cls, dev), nblocks=nblocks, integer=True)
+    y = plan.forward(_to(x, dev)).cpu().numpy()
+    ref = orc.forward_int(x, cls, codes)
+    assert np.array_equal(y.astype(np.int64), ref)
+    xi = plan.inverse(_to(y, dev)).cpu().numpy()
+    assert np.array_equal(xi.astype(np.int64), orc.inverse_int(ref, cls, codes))
+
+
+def test_integer_workload_in_place_and_edges():
+    """8x8 integer residuals (the 2^20-block workload's distribution, 2^16
+    blocks here), in place; then empty and ragged batches."""
+    import paper_2505_21728_amd as hygt
+    dev = _dev()
+    d, rounds, C = 6, 4, 35
+    rng = np.random.default_rng(77)
+    codes = rng.integers(0, 256, size=(C, rounds, d, 32)).astype(np.uint8)
+    x = synth.ar1_blocks(1 << 16, 8, seed=6).astype(np.int32)
+    cls = synth.classes(1 << 16, C)
+    _say("int workload in place")
+    plan = hygt.Plan(_to(codes, dev), _to(cls, dev), integer=True)
+    buf = _to(x, dev)
+    plan.forward(buf, out=buf)
+    assert np.array_equal(buf.cpu().numpy().astype(np.int64), orc.forward_int(x, cls, codes))
+    for nblocks in (0, 1, 63, 64, 65):
+        _say(f"int ragged B={nblocks}")
+        codes_s, xs, cs = _int_case(nblocks, 4, 2, 3, nblocks, 255)
+        p = hygt.Plan(_to(codes_s, dev), _to(cs, dev), nblocks=nblocks, integer=True)
+        ys = p.forward(_to(xs, dev)).cpu().numpy()
+        if nblocks:
+            assert np.array_equal(ys.astype(np.int64), orc.forward_int(xs, cs, codes_s))
+
+
+def test_integer_plan_rejects_float_ops():
+    import paper_2505_21728_amd as hygt
+    dev = _dev()
+    codes, x, cls = _int_case(64, 4, 2, 2, 1, 100)
+    plan = hygt.Plan(_to(codes, dev), _to(cls, dev), integer=True)
+    with pytest.raises(TypeError):
+        plan.forward(_to(x.astype(np.float32), dev))
+    with pytest.raises(ValueError):
+        plan.apply_permuted(_to(x, dev), hygt.HYGT_FORWARD,
+                            _to(np.zeros((2, 16), np.int32), dev))
+    with pytest.raises(TypeError):
+        hygt.Plan(_to(synth.angles(2, 2, 4), dev), _to(cls, dev), integer=True)
