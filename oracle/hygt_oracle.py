@@ -28,6 +28,12 @@ listed with its justification in the design notes):
   (eq. (6), eq. (9), Sec. IV).
 * Class indices are 0-based.
 
+* Variants: 8-bit angle codes (Fig. 6) map code q to (q - 128) pi / 128, and
+  the integer transform uses 14-bit fixed-point multipliers with outputs
+  rounded by an arithmetic shift. The paper gives neither the map nor the
+  word length and rounding, so those choices are parity unpinned; the
+  arithmetic built on them is pinned.
+
 Every function states the passage it follows. Parity pins for each function
 live in tests/test_oracle.py.
 """

@@ -551,6 +551,23 @@ def test_permutation_pass():
     assert np.allclose(z, x, rtol=0, atol=1e-10)
 
 
+def test_permutation_hand_example():
+    """N = 4 with zero angles (identity transform), worked by hand: output i
+    is coefficient perm[i]; the inverse puts coefficient perm[i] back; the
+    variance order sorts mean squares 1, 9, 0, 4 into 1, 3, 0, 2 and breaks
+    ties by index."""
+    zero = np.zeros((1, 1, 2, 2))
+    x = np.array([[10.0, 20.0, 30.0, 40.0]])
+    perm = np.array([[2, 0, 3, 1]])
+    assert orc.forward_permuted(x, None, zero, perm).tolist() == [[30.0, 10.0, 40.0, 20.0]]
+    assert orc.inverse_permuted(np.array([[30.0, 10.0, 40.0, 20.0]]), None, zero,
+                                perm).tolist() == [[10.0, 20.0, 30.0, 40.0]]
+    y = np.array([[1.0, 3.0, 0.0, 2.0], [1.0, -3.0, 0.0, -2.0]])
+    assert orc.variance_order(y, np.array([0, 0]), 1).tolist() == [[1, 3, 0, 2]]
+    ties = np.array([[1.0, -1.0, 0.0, 0.0]])
+    assert orc.variance_order(ties, np.array([0]), 2).tolist() == [[0, 1, 2, 3], [0, 1, 2, 3]]
+
+
 # ---------------------------------------------------------------------------
 # Integer arithmetic (Fig. 6): fixed-point multipliers, rounded butterflies
 # ---------------------------------------------------------------------------
