@@ -11,6 +11,8 @@
 
 #include "hygt_internal.h"
 
+static_assert(HYGT_MAX_SEGMENTS == hygt::kMaxSegments, "segment limits differ");
+
 namespace {
 
 using hygt::WsLayout;
@@ -37,6 +39,15 @@ bool overlap_ok(const float* x, const float* y, int64_t nblocks, int log2n) {
     return xa + bytes <= ya || ya + bytes <= xa;
 }
 
+// Class indices and angles (or codes) of a plan with blocks.
+int plan_inputs_ok(const int32_t* cls, const float* angles, const uint8_t* codes, int nclasses) {
+    if (angles == nullptr && codes == nullptr) return HYGT_EINVAL;
+    if (angles != nullptr && !aligned(angles, 4)) return HYGT_EINVAL;
+    if (cls == nullptr && nclasses != 1) return HYGT_EINVAL;
+    if (cls != nullptr && !aligned(cls, 4)) return HYGT_EINVAL;
+    return HYGT_OK;
+}
+
 int plan_any(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const float* angles,
              const uint8_t* codes, int integer, int nclasses, void* ws, size_t ws_bytes,
              hipStream_t stream) {
@@ -44,10 +55,7 @@ int plan_any(const int32_t* cls, int64_t nblocks, int log2n, int rounds, const f
     const WsLayout l = hygt::ws_layout(nblocks, log2n, rounds, nclasses);
     if (int s = check_workspace(ws, ws_bytes, l)) return s;
     if (nblocks == 0) return HYGT_OK;  // empty arrays may come as NULL pointers
-    if (angles == nullptr && codes == nullptr) return HYGT_EINVAL;
-    if (angles != nullptr && !aligned(angles, 4)) return HYGT_EINVAL;
-    if (cls == nullptr && nclasses != 1) return HYGT_EINVAL;
-    if (cls != nullptr && !aligned(cls, 4)) return HYGT_EINVAL;
+    if (int s = plan_inputs_ok(cls, angles, codes, nclasses)) return s;
     const hipError_t e = hygt::launch_plan(cls, nblocks, log2n, rounds, angles, codes, integer,
                                            nclasses, l, hygt::ws_ptrs(ws, l), stream);
     return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
@@ -210,14 +218,40 @@ int mixed_plan_impl(const hygt_segment* segs, int nseg, void* ws, size_t ws_byte
     size_t offsets[HYGT_MAX_SEGMENTS];
     const size_t total = mixed_layout(segs, nseg, offsets);
     if (ws == nullptr || ws_bytes < total || !aligned(ws, 256)) return HYGT_EWORKSPACE;
+    // Every segment with blocks gets its share of the same two launches.
+    hygt::PlanArgs a{};
+    int64_t count_wgs = 0, place_wgs = 0;
     for (int i = 0; i < nseg; ++i) {
         const hygt_segment& g = segs[i];
+        if (g.nblocks == 0) continue;
+        if (int s = plan_inputs_ok(g.cls, g.angles, nullptr, g.nclasses)) return s;
         const WsLayout l = hygt::ws_layout(g.nblocks, g.log2n, g.rounds, g.nclasses);
-        if (int s = plan_impl(g.cls, g.nblocks, g.log2n, g.rounds, g.angles, g.nclasses,
-                              static_cast<char*>(ws) + offsets[i], l.total, stream))
-            return s;
+        const hygt::WsPtrs p = hygt::ws_ptrs(static_cast<char*>(ws) + offsets[i], l);
+        hygt::PlanSeg& m = a.seg[a.nseg++];
+        m.cls = g.cls;
+        m.angles = g.angles;
+        m.hdr = p.hdr;
+        m.chunk_err = p.chunk_err;
+        m.counts = p.counts;
+        m.tile_class = p.tile_class;
+        m.perm = p.perm;
+        m.modes = p.modes;
+        m.coef = p.coef;
+        m.signs = p.signs;
+        m.nblocks = g.nblocks;
+        m.nchunks = l.nchunks;
+        m.chunk = l.chunk;
+        m.max_tiles = l.max_tiles;
+        m.count_begin = count_wgs;
+        m.place_begin = place_wgs;
+        m.log2n = g.log2n;
+        m.rounds = g.rounds;
+        m.nclasses = g.nclasses;
+        count_wgs += l.nchunks;
+        place_wgs += 2 * static_cast<int64_t>(g.nclasses) + l.nchunks;
     }
-    return HYGT_OK;
+    const hipError_t e = hygt::launch_plan_mixed(a, count_wgs, place_wgs, stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 
 int mixed_apply_impl(const hygt_segment* segs, int nseg, int direction, int config,

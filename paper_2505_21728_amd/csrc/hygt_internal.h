@@ -126,6 +126,45 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
                        const float* angles, const uint8_t* codes, int integer, int nclasses,
                        const WsLayout& l, const WsPtrs& p, hipStream_t stream);
 
+// Segments (block sizes) of a mixed batch, at most.
+constexpr int kMaxSegments = 4;
+
+// One batch (block size) of a fused mixed plan: its inputs, its part of the
+// workspace, and the first workgroup index of its share of either launch.
+struct PlanSeg {
+    const int32_t* cls;
+    const float* angles;
+    PlanHeader* hdr;
+    int32_t* chunk_err;
+    int32_t* counts;
+    int32_t* tile_class;
+    int32_t* perm;
+    int32_t* modes;
+    float* coef;
+    float* signs;
+    int64_t nblocks;
+    int64_t nchunks;
+    int64_t chunk;
+    int64_t max_tiles;
+    int64_t count_begin;  // first workgroup of launch A (counting)
+    int64_t place_begin;  // first workgroup of launch B (tables, then placing)
+    int log2n;
+    int rounds;
+    int nclasses;
+    int pad;
+};
+
+struct PlanArgs {
+    PlanSeg seg[kMaxSegments];
+    int nseg;
+    int pad;
+};
+
+// The plans of every segment with blocks in two launches of count_wgs and
+// place_wgs workgroups (hygt_plan.hip).
+hipError_t launch_plan_mixed(const PlanArgs& a, int64_t count_wgs, int64_t place_wgs,
+                             hipStream_t stream);
+
 // Integer arithmetic: multipliers with kIntFracBits fractional bits, outputs
 // rounded by adding half a unit and shifting right (floor).
 constexpr int kIntFracBits = 14;
@@ -153,7 +192,6 @@ hipError_t launch_backward(const float* y, const float* gy, float* gx, float* ga
 
 // Mixed batches: several block sizes, each a segment with its own plan,
 // transformed by one persistent launch (hygt_rotate.hip).
-constexpr int kMaxSegments = 4;
 struct MixedSeg {
     const float* x;
     float* y;

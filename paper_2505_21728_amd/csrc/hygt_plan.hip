@@ -304,34 +304,29 @@ __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(
     count_chunk(sh, k, cls, nblocks, chunk, nclasses, counts, chunk_err);
 }
 
-// Launch B: workgroups [0, 2C) build the multiplier tables of (direction,
-// class), which need nothing from launch A, so they run beside the placing
-// workgroups instead of before them; workgroup 2C + k places chunk k. Class
-// c's blocks fill tiles tile_base[c] .. in chunk order; inside a chunk their
-// order is that of the LDS counters (any order gives the same results,
-// block by block).
-__global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
-    const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
-    int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
-    int32_t* __restrict__ tile_class, int32_t* __restrict__ perm,
-    const float* __restrict__ angles, const uint8_t* __restrict__ codes, int log2n, int rounds,
-    int integer, int32_t* __restrict__ modes,
-    float* __restrict__ coef, float* __restrict__ signs) {
-    extern __shared__ __align__(16) int place_dyn[];
-    if (blockIdx.x < 2 * nclasses) {
-        const int wg = static_cast<int>(blockIdx.x);
-        if (integer) {
-            build_table_int(wg / nclasses, wg % nclasses, codes, log2n, rounds, nclasses, coef,
-                            signs, modes);
-            return;
-        }
-        build_table(*reinterpret_cast<TableShared*>(place_dyn), wg / nclasses, wg % nclasses,
-                    angles, codes, log2n, rounds, nclasses, coef, signs, modes);
+// Table builder of workgroup w < 2C of a placing launch: (direction, class) =
+// (w / C, w % C).
+__device__ __forceinline__ void build_tables_wg(int* place_dyn, int w, const float* __restrict__ angles,
+                                const uint8_t* __restrict__ codes, int log2n, int rounds,
+                                int integer, int nclasses, int32_t* __restrict__ modes,
+                                float* __restrict__ coef, float* __restrict__ signs) {
+    if (integer) {
+        build_table_int(w / nclasses, w % nclasses, codes, log2n, rounds, nclasses, coef, signs,
+                        modes);
         return;
     }
+    build_table(*reinterpret_cast<TableShared*>(place_dyn), w / nclasses, w % nclasses, angles,
+                codes, log2n, rounds, nclasses, coef, signs, modes);
+}
+
+// Places chunk k of one batch: its blocks' ids into their classes' tiles, and
+// the class of this chunk's share of the tile list.
+__device__ __forceinline__ void place_chunk(int* place_dyn, int64_t k, const int32_t* __restrict__ cls,
+                            int64_t nblocks, int nclasses, int64_t nchunks, int64_t chunk,
+                            int64_t max_tiles, const int32_t* __restrict__ counts,
+                            int32_t* __restrict__ tile_class, int32_t* __restrict__ perm) {
     const PlaceLds sh = place_lds(place_dyn, nchunks, nclasses);
     const int tid = threadIdx.x;
-    const int64_t k = blockIdx.x - 2 * static_cast<int64_t>(nclasses);
     const int64_t ncounts = nchunks * nclasses;
     const bool cached = place_counts_cached(nchunks, nclasses);
     // The first round of this chunk's class indices, loaded now so that their
@@ -440,6 +435,65 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
     }
 }
 
+
+// Launch B: workgroups [0, 2C) build the multiplier tables of (direction,
+// class), which need nothing from launch A, so they run beside the placing
+// workgroups instead of before them; workgroup 2C + k places chunk k. Class
+// c's blocks fill tiles tile_base[c] .. in chunk order; inside a chunk their
+// order is that of the LDS counters (any order gives the same results,
+// block by block).
+__global__ __launch_bounds__(kPlanThreads) void plan_place_kernel(
+    const int32_t* __restrict__ cls, int64_t nblocks, int nclasses, int64_t nchunks,
+    int64_t chunk, int64_t max_tiles, const int32_t* __restrict__ counts,
+    int32_t* __restrict__ tile_class, int32_t* __restrict__ perm,
+    const float* __restrict__ angles, const uint8_t* __restrict__ codes, int log2n, int rounds,
+    int integer, int32_t* __restrict__ modes,
+    float* __restrict__ coef, float* __restrict__ signs) {
+    extern __shared__ __align__(16) int place_dyn[];
+    const int64_t w = blockIdx.x;
+    if (w < 2 * nclasses) {
+        build_tables_wg(place_dyn, static_cast<int>(w), angles, codes, log2n, rounds, integer,
+                        nclasses, modes, coef, signs);
+        return;
+    }
+    place_chunk(place_dyn, w - 2 * static_cast<int64_t>(nclasses), cls, nblocks, nclasses,
+                nchunks, chunk, max_tiles, counts, tile_class, perm);
+}
+
+// The plans of up to HYGT_MAX_SEGMENTS batches (block sizes) in the same two
+// launches: the workgroups of segment s follow those of the segments before
+// it, in both launches, and each finds its segment by the first workgroup
+// indices of the segments (wave-uniform, at most four compares).
+__device__ __forceinline__ int plan_segment(const PlanArgs& a, int64_t w, bool place) {
+    int s = 0;
+    for (int i = 1; i < a.nseg; ++i)
+        if (w >= (place ? a.seg[i].place_begin : a.seg[i].count_begin)) s = i;
+    return s;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_count_mixed_kernel(PlanArgs a) {
+    __shared__ CountShared sh;
+    const int64_t w = blockIdx.x;
+    const PlanSeg& g = a.seg[plan_segment(a, w, false)];
+    const int64_t k = w - g.count_begin;
+    if (k == 0 && threadIdx.x == 0) g.hdr->nchunks = static_cast<int32_t>(g.nchunks);
+    count_chunk(sh, k, g.cls, g.nblocks, g.chunk, g.nclasses, g.counts, g.chunk_err);
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_place_mixed_kernel(PlanArgs a) {
+    extern __shared__ __align__(16) int place_dyn[];
+    const int64_t w = blockIdx.x;
+    const PlanSeg& g = a.seg[plan_segment(a, w, true)];
+    const int64_t local = w - g.place_begin;
+    if (local < 2 * g.nclasses) {
+        build_tables_wg(place_dyn, static_cast<int>(local), g.angles, nullptr, g.log2n, g.rounds,
+                        0, g.nclasses, g.modes, g.coef, g.signs);
+        return;
+    }
+    place_chunk(place_dyn, local - 2 * static_cast<int64_t>(g.nclasses), g.cls, g.nblocks,
+                g.nclasses, g.nchunks, g.chunk, g.max_tiles, g.counts, g.tile_class, g.perm);
+}
+
 }  // namespace
 
 hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int rounds,
@@ -461,6 +515,27 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
                        dim3(kPlanThreads), lds, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
                        l.max_tiles, p.counts, p.tile_class, p.perm, angles, codes, log2n,
                        rounds, integer, p.modes, p.coef, p.signs);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_mixed(const PlanArgs& a, int64_t count_wgs, int64_t place_wgs,
+                             hipStream_t stream) {
+    if (count_wgs == 0) return hipSuccess;
+    hipLaunchKernelGGL(plan_count_mixed_kernel, dim3(static_cast<unsigned>(count_wgs)),
+                       dim3(kPlanThreads), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t lds = 0;
+    for (int i = 0; i < a.nseg; ++i)
+        lds = std::max(lds, place_lds_bytes(a.seg[i].nchunks, a.seg[i].nclasses));
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(plan_place_mixed_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(plan_place_mixed_kernel, dim3(static_cast<unsigned>(place_wgs)),
+                       dim3(kPlanThreads), lds, stream, a);
     return hipGetLastError();
 }
 

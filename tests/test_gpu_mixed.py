@@ -132,3 +132,31 @@ def test_mixed_graph_replays():
             _say(f"[gpu] graph replay {rep} matches the eager launch")
     finally:
         g.close()
+
+
+def test_mixed_plan_with_empty_segment_and_class_counts():
+    """One fused plan over segments of different class counts, with an empty
+    segment between them and a single-class segment without class indices:
+    each segment's workgroups must find their own segment."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    spec = [(4, 2, 3, 4099, True), (6, 4, 7, 0, True), (5, 3, 1, 777, False),
+            (8, 2, 35, 300, True)]
+    segs, plain = [], []
+    for i, (d, r, c, nb, with_cls) in enumerate(spec):
+        _say(f"[gpu] mixed empty-segment case: segment {i} d={d} C={c} B={nb}")
+        ang = _to(synth.angles(c, r, d, seed=40 + i), dev)
+        x = _to(synth.gaussian_blocks(nb, 1 << d, seed=50 + i), dev)
+        cls = _to(synth.classes(nb, c, seed=60 + i), dev) if with_cls else None
+        segs.append((x, cls, ang))
+        if nb:
+            plan = hygt.Plan(ang, cls, nblocks=nb)
+            plain.append(plan.forward(x).cpu().numpy())
+        else:
+            plain.append(np.zeros((0, 1 << d), np.float32))
+    mb = hygt.MixedBatch(segs)
+    mb.apply(0)
+    torch.cuda.synchronize()
+    for i, (y, p) in enumerate(zip(mb.y, plain)):
+        assert np.array_equal(y.cpu().numpy(), p), f"segment {i}"
+    mb.check()
