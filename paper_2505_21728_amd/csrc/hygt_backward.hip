@@ -50,13 +50,43 @@ __global__ __launch_bounds__(kPrepThreads) void backward_prep_kernel(
     }
 }
 
+// Lane exchanges that stay in the vector ALU (no LDS): the gfx950 row and
+// half swaps, and DPP rotations inside rows of 16 lanes.
+__device__ __forceinline__ float swap_sum32(float x, float y) {
+    // x: lanes 32-63 take y's lanes 0-31; y: lanes 0-31 take x's lanes 32-63
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap_sum16(float x, float y) {
+    // the odd rows of x trade places with the even rows of y
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Value of lane (l - R) mod 16 of the same row, for lane l.
+template <int R>
+__device__ __forceinline__ float row_ror(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + R, 0xF, 0xF, true));
+}
+
 // Sum over the 64 lanes of a[j], j < H, one value per pair. On return, the
 // lanes whose low (6 - log2 H) bits are zero own pair j = lane >> (6 - log2 H)
 // and hold its sum.
+//
+// Transposed halving along lane bits 5, 4, ..., 6 - log2 H: at the step for
+// bit b a lane keeps the half of its values that its bit b selects (the
+// upper half where the bit is set) and adds the partner lane's (lane ^ 2^b)
+// copy of that half. For bits 5 and 4 one swap instruction moves both halves
+// at once; for lower bits each lane rotates both halves within its row and
+// keeps the sum it needs. The lanes that end up holding the same pair are
+// then summed into the lowest of them.
 template <int H>
 __device__ __forceinline__ float lane_sum(float (&a)[H], int lane) {
     constexpr int LH = H == 1 ? 0 : H == 2 ? 1 : H == 4 ? 2 : H == 8 ? 3 : H == 16 ? 4 : 5;
-    // transposed halving along lane bits 5, 4, ..., 6 - LH
     StaticFor<0, LH>::run([&](auto ss) {
         constexpr int s = decltype(ss)::value;
         constexpr int K = H >> (s + 1);  // values kept after this step
@@ -64,16 +94,29 @@ __device__ __forceinline__ float lane_sum(float (&a)[H], int lane) {
         const bool hi = (lane >> b) & 1;
         StaticFor<0, K>::run([&](auto ii) {
             constexpr int i = decltype(ii)::value;
-            const float send = hi ? a[i] : a[i + K];
-            const float keep = hi ? a[i + K] : a[i];
-            a[i] = keep + __shfl_xor(send, 1 << b, 64);
+            if constexpr (b == 5) {
+                a[i] = swap_sum32(a[i], a[i + K]);
+            } else if constexpr (b == 4) {
+                a[i] = swap_sum16(a[i], a[i + K]);
+            } else {
+                // bit clear: partner l + 2^b, bit set: partner l - 2^b
+                const float lo_sum = a[i] + row_ror<16 - (1 << b)>(a[i]);
+                const float hi_sum = a[i + K] + row_ror<(1 << b)>(a[i + K]);
+                a[i] = hi ? hi_sum : lo_sum;
+            }
         });
     });
-    // the lanes that now hold the same pair: sum over the remaining bits
+    // bits 0 .. 5 - LH: lane l adds the partial sum of lane l + 2^b, so that
+    // the lowest lane of each group ends with the group's total
     float v = a[0];
     StaticFor<0, 6 - LH>::run([&](auto bb) {
-        constexpr int b = 5 - LH - decltype(bb)::value;
-        v += __shfl_xor(v, 1 << b, 64);
+        constexpr int b = decltype(bb)::value;
+        if constexpr (b == 5)
+            v = swap_sum32(v, v);
+        else if constexpr (b == 4)
+            v = swap_sum16(v, v);
+        else
+            v += row_ror<16 - (1 << b)>(v);
     });
     return v;
 }
