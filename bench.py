@@ -336,17 +336,63 @@ def _serve_workload(torch):
     return stats
 
 
-def _cpu_baseline(x, cls, ang, sample):
+def _oracle_fwd_inv(args):
     from oracle import hygt_oracle as orc
 
-    xs, cs = x[:sample], cls[:sample]
-    t0 = time.perf_counter()
+    xs, cs, ang = args
     y = orc.forward(xs, cs, ang)
     orc.inverse(y, cs, ang)
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "blocks/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} blocks of the batch, forward + inverse, FP64 NumPy, "
-                      f"one process ({dt:.1f} s)"}
+    return xs.shape[0]
+
+
+def _cpu_baseline(x, cls, ang, sample):
+    """The oracle on the host, forward + inverse: one process on the first
+    `sample` blocks, then one process per available core (at most 16) on
+    `sample` blocks each, contiguous ranges of the batch. Runs before the GPU
+    is touched, so the worker processes are forked from a process without
+    HIP state."""
+    import multiprocessing as mp
+
+    t0 = time.perf_counter()
+    _oracle_fwd_inv((x[:sample], cls[:sample], ang))
+    dt1 = time.perf_counter() - t0
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts = [(x[i * sample:(i + 1) * sample], cls[i * sample:(i + 1) * sample], ang)
+             for i in range(procs) if (i + 1) * sample <= x.shape[0]]
+    with mp.get_context("fork").Pool(len(parts)) as pool:
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_fwd_inv, parts))
+        dtp = time.perf_counter() - t0
+    return {"value": done / dtp, "unit": "blocks/s", "cores": len(parts), "kind": "oracle",
+            "sample": f"{len(parts)} processes, each forward + inverse of {sample} consecutive "
+                      f"blocks of the batch ({done} blocks, {dtp:.1f} s), FP64 NumPy",
+            "single_process_value": sample / dt1,
+            "single_process_sample": f"first {sample} blocks, one process ({dt1:.1f} s)"}
+
+
+def _copy_ceiling(torch, xs, out, steps):
+    """Cache-cold device-to-device copy of one batch (256 MiB), cycling over
+    the input ring like the timed steps: the practical HBM ceiling."""
+    stream = torch.cuda.current_stream()
+    for k in range(3):
+        out.copy_(xs[k % len(xs)])
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        out.copy_(xs[i % len(xs)])
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    med = ms[len(ms) // 2]
+    return {"median_ms": med, "gbps": 2 * out.numel() * 4 / (med / 1e3) / 1e9}
+
+
+def _pcts(vals):
+    v = sorted(vals)
+    pick = lambda q: v[min(len(v) - 1, int(q * (len(v) - 1) + 0.5))]
+    return {"p10": pick(0.1), "p50": pick(0.5), "p90": pick(0.9)}
 
 
 def main():
@@ -357,20 +403,26 @@ def main():
               "share with no communication)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    from paper_2505_21728_amd import synth
+
+    ang = x = cls = cpu = None
+    if not args.copy_calibration:
+        ang = synth.angles(NCLASSES, ROUNDS, LOG2N)
+        x = synth.ar1_blocks(NBLOCKS, 8)
+        cls = synth.classes(NBLOCKS, NCLASSES)
+        if args.cpu_sample > 0:
+            # before anything touches the GPU (see _cpu_baseline)
+            cpu = _cpu_baseline(x, cls, ang, min(args.cpu_sample, NBLOCKS))
+
     import torch
 
     import paper_2505_21728_amd as hygt
-    from paper_2505_21728_amd import synth
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         _copy_calibration(torch, dev)
         return
 
-    ang = synth.angles(NCLASSES, ROUNDS, LOG2N)
-    x = synth.ar1_blocks(NBLOCKS, 8)
-    cls = synth.classes(NBLOCKS, NCLASSES)
     x0 = torch.from_numpy(x).to(dev)
     c0 = torch.from_numpy(cls).to(dev)
     shift = NBLOCKS // RING + 12345
@@ -385,9 +437,11 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
 
     def step(k, events=None):
+        if events:
+            events[4].record(stream)
         plan = hygt.Plan(at, cs[k % RING], workspace=ws)
         if events:
             events[0].record(stream)
@@ -398,6 +452,7 @@ def main():
         plan.inverse(yt, out=zt)
         if events:
             events[3].record(stream)
+            events[5].record(stream)
         return plan
 
     for i in range(args.warmup):
@@ -413,23 +468,23 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
-    inv_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / args.steps
+    fwd_all = [e[0].elapsed_time(e[1]) for e in ev]
+    inv_all = [e[2].elapsed_time(e[3]) for e in ev]
+    step_all = [e[4].elapsed_time(e[5]) for e in ev]
+    fwd_ms = sum(fwd_all) / args.steps
+    inv_ms = sum(inv_all) / args.steps
     ms_per_step = 1e3 * elapsed / args.steps
     value = NBLOCKS / (ms_per_step / 1e3)
     launch_bytes = NBLOCKS * BYTES_PER_BLOCK
     achieved = launch_bytes / (fwd_ms / 1e3) / 1e9
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
+    copy = _copy_ceiling(torch, xs, zt, args.steps)
     klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
     variants = _variants(torch, hygt, at, cs, xs, args.steps)
     grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
     mixed = _mixed_workload(torch, hygt, args.steps)
     served = _serve_workload(torch)
-
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = _cpu_baseline(x, cls, ang, min(args.cpu_sample, NBLOCKS))
 
     out = {
         "metric": METRIC,
@@ -452,9 +507,12 @@ def main():
         "step_pct_peak": 100.0 * step_gbps / HBM_PEAK_GBPS,
         "fwd_ms": fwd_ms,
         "inv_ms": inv_ms,
+        "event_ms": {"step": _pcts(step_all), "fwd": _pcts(fwd_all), "inv": _pcts(inv_all)},
+        "copy_ceiling": copy,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": _measured_traffic(),
+                     "frac_of_copy_ceiling": achieved / copy["gbps"],
                      "kernel": "rotate_kernel<6,0,4> (forward)",
                      "bytes_per_launch": launch_bytes,
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},
