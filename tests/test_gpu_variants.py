@@ -110,6 +110,26 @@ def test_permutation_pass(d, rounds, nblocks):
     _close(back, x.astype(np.float64), "permuted round trip")
 
 
+def test_permutation_entries_taken_modulo_n():
+    """Entries outside [0, N) are used modulo N (the header's contract):
+    shifting every entry by +N or -N changes nothing, bit for bit."""
+    import paper_2505_21728_amd as hygt
+    dev = _dev()
+    d, rounds, C, nblocks = 5, 2, 3, 500
+    _say("perm entries modulo N")
+    ang = synth.angles(C, rounds, d, seed=21)
+    x, cls = _case(nblocks, d, rounds, C, 22)
+    perm = _perms(C, 32, np.random.default_rng(23))
+    plan = hygt.Plan(_to(ang, dev), _to(cls, dev), nblocks=nblocks)
+    xt = _to(x, dev)
+    ref = plan.apply_permuted(xt, hygt.HYGT_FORWARD, _to(perm, dev))
+    for shift in (32, -32, 64):
+        got = plan.apply_permuted(xt, hygt.HYGT_FORWARD, _to((perm + shift).astype(np.int32), dev))
+        assert torch.equal(got, ref), shift
+        inv = plan.apply_permuted(ref, hygt.HYGT_INVERSE, _to((perm + shift).astype(np.int32), dev))
+        assert torch.equal(inv, plan.apply_permuted(ref, hygt.HYGT_INVERSE, _to(perm, dev)))
+
+
 def test_permutation_variance_order_in_place():
     """The ordering of Fig. 4 (decreasing coefficient variance per class),
     applied in place; positions that tie are compared through the values."""
