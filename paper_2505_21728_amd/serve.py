@@ -5,12 +5,15 @@ size, with a class per block). The server keeps every size's angle table on
 the device and runs batches in a ring of slots; each slot has its own stream,
 staging buffers whose capacity caps the memory a batch may use, and
 workspace. Whenever a slot is free, the requests waiting in the queue are
-admitted first come, first served while they fit its capacity, copied into
-the slot's per-size buffers, planned, and transformed by one mixed launch
-(hygt_mixed_plan + hygt_mixed_apply). Requests that arrive while batches run
-wait for the next free slot, so batches overlap on the device. Each result is
-copied into its request's own output and stamped with the time its batch
-finished on the device.
+admitted first come, first served while they fit its capacity, planned, and
+transformed by one mixed launch (hygt_mixed_plan + hygt_mixed_apply).
+A batch of at most four requests (the segments one launch takes) is
+transformed in place of its requests' own tensors: each request is a
+segment, read from its input and written to its output, with no copies.
+Larger batches are gathered into the slot's per-size buffers, and each
+result is copied out into its request's output. Requests that arrive while
+batches run wait for the next free slot, so batches overlap on the device.
+Each result is stamped with the time its batch finished on the device.
 
 Every block's result depends only on the block, its class and the angles,
 so a request's output is bit-identical whether it is served alone or in any
@@ -39,6 +42,7 @@ class Request:
     cls: object               # [nblocks] int32, device
     arrival: float            # host time (perf_counter seconds)
     out: object = None        # [nblocks, N] float32, filled on completion
+    ready: object = None      # optional event after which x and cls may be read
     done: float = None        # device completion time mapped to host seconds
     batch: int = -1           # index of the batch that served it
 
@@ -54,6 +58,7 @@ class _Slot:
     y: dict
     cls: dict
     workspace: object
+    handle: int = 0           # the stream's HIP handle
     event: object = None
     requests: list = field(default_factory=list)
     busy: bool = False
@@ -76,6 +81,14 @@ class Server:
             a = self.tables[d]
             seg_items.append((0, 0, 0, 0, self.capacity[d], d, int(a.shape[1]), int(a.shape[0])))
         ws_bytes = _abi.hygt_mixed_workspace_bytes(_abi.segments(seg_items), len(seg_items))
+        # a zero-copy batch: up to HYGT_MAX_SEGMENTS requests of any sizes,
+        # each at most its size's capacity
+        for d in self.sizes:
+            a = self.tables[d]
+            direct = [(0, 0, 0, 0, self.capacity[d], d, int(a.shape[1]),
+                       int(a.shape[0]))] * _abi.HYGT_MAX_SEGMENTS
+            ws_bytes = max(ws_bytes, _abi.hygt_mixed_workspace_bytes(_abi.segments(direct),
+                                                                     len(direct)))
         self.slots = []
         for _ in range(slots):
             self.slots.append(_Slot(
@@ -85,9 +98,14 @@ class Server:
                 cls={d: torch.zeros(self.capacity[d], dtype=torch.int32, device=dev)
                      for d in self.sizes},
                 workspace=torch.empty(ws_bytes, dtype=torch.uint8, device=dev)))
+            self.slots[-1].handle = int(self.slots[-1].stream.cuda_stream)
+        self.ws_bytes = ws_bytes
+        self._meta = {d: (int(self.tables[d].data_ptr()), int(self.tables[d].shape[1]),
+                          int(self.tables[d].shape[0])) for d in self.sizes}
         self.queue = collections.deque()
         self.batches = 0
         self.busy_batches = []    # (start_event, end_event) per batch, for device busy time
+        self.dispatch_s = 0.0     # host time spent starting batches
         self.config = self._tune() if config is None else config
         # device time origin: host time t0 <-> event e0
         torch.cuda.synchronize(dev)
@@ -106,10 +124,23 @@ class Server:
         return cfg
 
     def submit(self, req: Request) -> None:
+        """Queues a request. Its x and cls must be complete on the device, or
+        req.ready must be an event recorded after the work that writes them
+        (the batch's stream then waits for it). The server keeps the request,
+        and so its tensors, until its batch has finished."""
         if req.log2n not in self.tables:
             raise ValueError(f"no angle table for log2n = {req.log2n}")
         if req.nblocks > self.capacity[req.log2n]:
             raise ValueError("request larger than a slot's capacity")
+        torch = _torch()
+        x, c = req.x, req.cls
+        if not (isinstance(x, torch.Tensor) and x.device == self.device and
+                x.dtype == torch.float32 and x.dim() == 2 and x.shape[1] == 1 << req.log2n and
+                x.is_contiguous()):
+            raise ValueError("x must be a contiguous [B, N] float32 tensor on the server's device")
+        if not (isinstance(c, torch.Tensor) and c.device == self.device and
+                c.dtype == torch.int32 and c.shape == (x.shape[0],) and c.is_contiguous()):
+            raise ValueError("cls must be a contiguous [B] int32 tensor on the server's device")
         self.queue.append(req)
 
     def _device_time(self, ev) -> float:
@@ -130,7 +161,9 @@ class Server:
             if not self.queue:
                 break
             if not s.busy:
+                t = time.perf_counter()
                 self._dispatch(s)
+                self.dispatch_s += time.perf_counter() - t
         return completed
 
     def _dispatch(self, s: _Slot) -> None:
@@ -146,26 +179,51 @@ class Server:
             used[r.log2n] += r.nblocks
         if not taken:
             return
+        direct = len(taken) <= _abi.HYGT_MAX_SEGMENTS
         with torch.cuda.stream(s.stream):
             start = torch.cuda.Event(enable_timing=True)
             start.record(s.stream)
-            for r, off in taken:
-                s.x[r.log2n][off:off + r.nblocks].copy_(r.x, non_blocking=True)
-                s.cls[r.log2n][off:off + r.nblocks].copy_(r.cls, non_blocking=True)
-            segs = [(s.x[d][:used[d]], s.y[d][:used[d]], s.cls[d][:used[d]], self.tables[d])
-                    for d in self.sizes if used[d] > 0]
-            mb = MixedBatch(segs, stream=s.stream, workspace=s.workspace, config=self.config)
-            mb.apply(HYGT_FORWARD, stream=s.stream)
-            for r, off in taken:
+            for r, _ in taken:
+                if r.ready is not None:
+                    s.stream.wait_event(r.ready)
                 r.out = torch.empty_like(r.x)
-                r.out.copy_(s.y[r.log2n][off:off + r.nblocks], non_blocking=True)
                 r.batch = self.batches
+            if direct:
+                self._launch(s, [(r.x.data_ptr(), r.out.data_ptr(), r.cls.data_ptr(),
+                                  r.nblocks, r.log2n) for r, _ in taken])
+            else:
+                self._gathered(s, taken, used)
             s.event = torch.cuda.Event(enable_timing=True)
             s.event.record(s.stream)
         self.busy_batches.append((start, s.event))
         s.requests = [r for r, _ in taken]
         s.busy = True
         self.batches += 1
+
+    def _gathered(self, s: _Slot, taken: list, used: dict) -> None:
+        """More requests than one launch has segments: gathered per size into
+        the slot's buffers, transformed, copied out."""
+        for r, off in taken:
+            s.x[r.log2n][off:off + r.nblocks].copy_(r.x, non_blocking=True)
+            s.cls[r.log2n][off:off + r.nblocks].copy_(r.cls, non_blocking=True)
+        self._launch(s, [(s.x[d].data_ptr(), s.y[d].data_ptr(), s.cls[d].data_ptr(), used[d], d)
+                         for d in self.sizes if used[d] > 0])
+        for r, off in taken:
+            r.out.copy_(s.y[r.log2n][off:off + r.nblocks], non_blocking=True)
+
+    def _launch(self, s: _Slot, parts: list) -> None:
+        """Plan + one mixed launch on the slot's stream over (x, y, cls,
+        nblocks, log2n) segments whose tensors submit() has checked."""
+        items = []
+        for x, y, c, nb, d in parts:
+            ang, rounds, nclasses = self._meta[d]
+            items.append((x, y, c, ang, nb, d, rounds, nclasses))
+        segs = _abi.segments(items)
+        ws = s.workspace.data_ptr()
+        _abi._check(_abi.hygt_mixed_plan(segs, len(items), ws, self.ws_bytes, s.handle),
+                    "hygt_mixed_plan")
+        _abi._check(_abi.hygt_mixed_apply(segs, len(items), HYGT_FORWARD, self.config, ws,
+                                          self.ws_bytes, s.handle), "hygt_mixed_apply")
 
     def drain(self) -> None:
         while self.queue or any(s.busy for s in self.slots):
@@ -197,7 +255,8 @@ def run_poisson(server: Server, requests: list, rate: float, seed: int = 4) -> d
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
             "blocks_per_s": blocks / (t_end - t_start), "wall_s": t_end - t_start,
-            "device_busy_s": busy, "offered_rate": rate}
+            "device_busy_s": busy, "offered_rate": rate,
+            "host_dispatch_us_per_batch": 1e6 * server.dispatch_s / max(server.batches, 1)}
 
 
 # Size mix of the serving workload: 4x4 : 8x8 : 16x16 blocks = 8 : 4 : 1.

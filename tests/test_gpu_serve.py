@@ -49,3 +49,34 @@ def test_served_results_match_alone():
         assert torch.equal(alone, r.out), f"request {r.rid}"
     with pytest.raises(ValueError):
         srv.submit(serve.Request(rid=-1, log2n=4, x=pools[4][:3001], cls=None, arrival=0.0))
+
+
+def test_zero_copy_and_gathered_batches():
+    """A batch of at most four requests runs on the requests' own tensors; a
+    larger one goes through the slot's buffers. Both give every request's
+    result bit for bit."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    from paper_2505_21728_amd import serve
+
+    tables, pools = {}, {}
+    for i, (d, _) in enumerate(serve.SERVE_MIX):
+        tables[d] = torch.from_numpy(synth.angles(7, 2, d, seed=10 + i)).to(dev)
+        w = 1 << (d // 2)
+        pools[d] = torch.from_numpy(synth.ar1_blocks(3000, w, seed=20 + i)).to(dev)
+    srv = serve.Server(tables, capacity={4: 4000, 6: 4000, 8: 4000}, slots=1)
+    many = serve.make_requests(12, tables, pools, seed=3, min_blocks=16, max_blocks=200)
+    for r in many:
+        srv.submit(r)                    # all queued before the first dispatch
+    srv.drain()
+    assert len({r.batch for r in many}) == 1          # one gathered batch of 12
+    one = serve.make_requests(3, tables, pools, seed=4, min_blocks=100, max_blocks=900)
+    for r in one:
+        srv.submit(r)
+    srv.drain()
+    assert len({r.batch for r in one}) == 1           # one zero-copy batch of 3
+    torch.cuda.synchronize()
+    for r in many + one:
+        print(f"[gpu] serve check request {r.rid} batch {r.batch}", flush=True)
+        alone = hygt.Plan(tables[r.log2n], r.cls).forward(r.x)
+        assert torch.equal(alone, r.out), f"request {r.rid} batch {r.batch}"
