@@ -277,3 +277,23 @@ def test_config2_full_size_sampled():
     # norms preserved (orthogonality) on all blocks
     ny = y.double().pow(2).sum(1).sqrt()
     assert float(((ny - den).abs() / den.clamp_min(1e-300)).max()) <= TOL
+
+
+@pytest.mark.parametrize("d,rounds,nclasses,nb", [
+    (4, 2, 4096, 20000),   # every class index; per-chunk counts too many for LDS
+    (6, 64, 3, 700),       # the most rounds (looping kernel)
+    (8, 64, 2, 300),       # the most rounds at the largest blocks (split tiles)
+])
+def test_limits(d, rounds, nclasses, nb):
+    """The largest class count and round count the library accepts."""
+    dev = _dev()
+    hygt = _hygt()
+    assert nclasses <= hygt.HYGT_MAX_CLASSES and rounds <= hygt.HYGT_MAX_ROUNDS
+    _say(f"[gpu] limits d={d} R={rounds} C={nclasses} nb={nb}")
+    rng = np.random.default_rng(1000 + d)
+    x = synth.gaussian_blocks(nb, 1 << d, seed=1100 + d)
+    cls = rng.integers(0, nclasses, nb).astype(np.int32)
+    ang = synth.angles(nclasses, rounds, d, seed=1200 + d)
+    y, z = _run(x, cls, ang, dev)
+    _assert_close(y, orc.forward(x, cls, ang), f"limits d={d} forward")
+    _assert_close(z, x.astype(np.float64), f"limits d={d} round trip")
