@@ -338,7 +338,7 @@ def class_log_variance_grad(y, cls, nclasses: int, eps: float = 1e-6) -> np.ndar
     return g
 
 
-def backward(y, gy, cls, angles):
+def backward(y, gy, cls, angles, with_mass=False):
     """Reverse-mode derivative of forward().
 
     Given the outputs y = forward(x, cls, angles) and gy = dL/dy, returns
@@ -351,6 +351,11 @@ def backward(y, gy, cls, angles):
     y_m = c x_m + s x_n, y_n = -s x_m + c x_n:
         dy_m/dtheta = y_n and dy_n/dtheta = -y_m, so dL/dtheta = g_m y_n - g_n y_m;
         (dL/dx_m, dL/dx_n) = (c g_m - s g_n, s g_m + c g_n), the inverse rotation of g.
+
+    With with_mass, also returns the summed magnitudes of the terms behind
+    each angle's gradient, sum over the class's blocks of |g_m y_n| + |g_n y_m|
+    (same layout as gangles): the scale against which a floating-point sum
+    of those terms has its error bounded.
     """
     y, cls, angles, rounds, d = _check(y, cls, angles)
     g = np.array(gy, dtype=np.float64, copy=True)
@@ -358,6 +363,7 @@ def backward(y, gy, cls, angles):
         raise ValueError("gy must have the shape of y")
     v = y.copy()
     gangles = np.zeros_like(angles)
+    mass = np.zeros_like(angles)
     for r in reversed(range(rounds)):
         for k in reversed(range(d)):
             m, n = pair_indices(d, k)
@@ -366,12 +372,17 @@ def backward(y, gy, cls, angles):
             s = np.sin(theta)
             contrib = g[:, m] * v[:, n] - g[:, n] * v[:, m]      # [B, N/2]
             np.add.at(gangles[:, r, k, :], cls, contrib)
+            if with_mass:
+                np.add.at(mass[:, r, k, :], cls,
+                          np.abs(g[:, m] * v[:, n]) + np.abs(g[:, n] * v[:, m]))
             ym, yn = v[:, m].copy(), v[:, n].copy()
             v[:, m] = c * ym - s * yn
             v[:, n] = s * ym + c * yn
             gm, gn = g[:, m].copy(), g[:, n].copy()
             g[:, m] = c * gm - s * gn
             g[:, n] = s * gm + c * gn
+    if with_mass:
+        return g, gangles, mass
     return g, gangles
 
 

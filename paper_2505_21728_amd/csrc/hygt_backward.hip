@@ -11,9 +11,18 @@
 //   dL/dtheta = g_m y_n - g_n y_m
 //   (dL/dx_m, dL/dx_n) = (c g_m - s g_n, s g_m + c g_n)
 //
+// Both the recovered inputs and dL/dx are the inverse rotation (G^T) of the
+// pass's outputs and output gradients. So y and g both run through the
+// inverse transform's lifting tables (three FMAs per pair each; see
+// hygt_table.h), which a preparation launch builds from the angles, and
+// carry the same stored signs s: stored values are s times true ones. A
+// pair's stored contribution g_m y_n - g_n y_m is then s_m s_n times the
+// true one, so the pair's summed contribution is negated where the table
+// records that the pair's two signs differ, and dL/dx takes the final signs.
+//
 // Mapping as in the rotation kernels: one wavefront per class-uniform tile of
 // 64 blocks, one lane per block holding the block's y and g (2N registers, so
-// N <= 64), the pass's (cos, sin) pairs as wave-uniform scalar operands. The
+// N <= 64), the pass's lifting multipliers as wave-uniform scalar operands. The
 // N/2 angle contributions of a pass are summed over the 64 lanes by a
 // transposed halving: at each step a lane keeps half of its values and adds
 // the partner lane's copy of that half, so after log2(N/2) steps each lane
@@ -22,6 +31,7 @@
 // (FP32 atomics: the order of the additions, so the last bits of the
 // gradient, varies from run to run).
 
+#include "hygt_table.h"
 #include "hygt_tile.h"
 
 namespace hygt {
@@ -30,24 +40,24 @@ namespace {
 using namespace tile;
 
 constexpr int kBwdWaves = 4;
-constexpr int kBwdWavesPerSimd = 2;
+constexpr int kBwdWavesPerSimd = 3;
 constexpr int kPrepThreads = 256;
 
-// Workgroup c: cos and sin (FP64, rounded once to FP32) of every angle of
-// class c, in the angles' own layout (forward pass order), and the class's
+// Workgroup c: the inverse-direction lifting table of class c from the
+// angles given (with the per-pass sign-difference masks), and the class's
 // gradient set to zero.
 __global__ __launch_bounds__(kPrepThreads) void backward_prep_kernel(
-    const float* __restrict__ angles, int log2n, int rounds, float* __restrict__ trig,
+    const float* __restrict__ angles, int log2n, int rounds, float* __restrict__ bcoef,
+    uint32_t* __restrict__ bflip, float* __restrict__ bsigns, int32_t* __restrict__ bmodes,
     float* __restrict__ gangles) {
+    __shared__ table::TableShared sh;
     const int64_t c = blockIdx.x;
-    const int per = rounds * log2n * (1 << (log2n - 1));
-    for (int e = threadIdx.x; e < per; e += blockDim.x) {
-        const int64_t a = c * per + e;
-        const double th = static_cast<double>(angles[a]);
-        trig[2 * a + 0] = static_cast<float>(cos(th));
-        trig[2 * a + 1] = static_cast<float>(sin(th));
-        gangles[a] = 0.0f;
-    }
+    const int n = 1 << log2n;
+    const int passes = rounds * log2n;
+    table::build_table(sh, 1, static_cast<int>(c), angles, nullptr, log2n, rounds,
+                       bcoef + c * passes * n, bsigns + c * n, bmodes + c, bflip + c * passes);
+    const int per = passes * (n / 2);
+    for (int e = threadIdx.x; e < per; e += blockDim.x) gangles[c * per + e] = 0.0f;
 }
 
 // Lane exchanges that stay in the vector ALU (no LDS): the gfx950 row and
@@ -126,7 +136,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(
 void backward_kernel(const float* __restrict__ y, const float* __restrict__ gy,
                      float* __restrict__ gx, float* __restrict__ gangles, int64_t nblocks,
                      int rounds, int64_t max_tiles, const int32_t* __restrict__ tile_class,
-                     const int32_t* __restrict__ perm, const float* __restrict__ trig) {
+                     const int32_t* __restrict__ perm, const float* __restrict__ bcoef,
+                     const uint32_t* __restrict__ bflip, const float* __restrict__ bsigns,
+                     const int32_t* __restrict__ bmodes) {
     using G = TileGeo<D>;
     constexpr int N = 1 << D;
     constexpr int H = N / 2;
@@ -157,32 +169,46 @@ void backward_kernel(const float* __restrict__ y, const float* __restrict__ gy,
         load_row<D>(gy, blk, g);
     }
 
-    const int64_t per_class = static_cast<int64_t>(rounds) * D * H;
-    const float* tc = trig + 2 * c * per_class;
-    float* gc = gangles + c * per_class;
+    const int64_t passes = static_cast<int64_t>(rounds) * D;
+    ctab_f tc = as_ctab(bcoef) + c * passes * N;
+    ctab_i fc = as_ctab(reinterpret_cast<const int32_t*>(bflip)) + c * passes;
+    float* gc = gangles + c * passes * H;
     const bool owner = (lane & ((1 << (6 - LH)) - 1)) == 0;
     const int my_pair = lane >> (6 - LH);
-    for (int r = rounds - 1; r >= 0; --r) {
+    // rr-th round of the walk = forward round rounds-1-rr; its passes K = D-1 .. 0
+    for (int rr = 0; rr < rounds; ++rr) {
+        const int r = rounds - 1 - rr;
         StaticFor<0, D>::run([&](auto kk) {
             constexpr int K = D - 1 - decltype(kk)::value;
-            const float* cp = tc + static_cast<int64_t>(r * D + K) * N;
+            const int64_t p = static_cast<int64_t>(rr) * D + decltype(kk)::value;
+            ctab_f cp = tc + p * N;
+            const uint32_t flip = static_cast<uint32_t>(fc[p]);
             float contrib[H];
             StaticFor<0, H>::run([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
                 constexpr int m = ins0(j, K);
                 constexpr int n = m + (1 << K);
-                const float cs = cp[2 * j];
-                const float sn = cp[2 * j + 1];
+                const float pm = cp[2 * j];
+                const float qm = cp[2 * j + 1];
                 contrib[j] = fmaf(g[m], v[n], -(g[n] * v[m]));
-                const float vm = v[m], vn = v[n];
-                v[m] = fmaf(cs, vm, -(sn * vn));
-                v[n] = fmaf(sn, vm, cs * vn);
-                const float gm = g[m], gn = g[n];
-                g[m] = fmaf(cs, gm, -(sn * gn));
-                g[n] = fmaf(sn, gm, cs * gn);
+                v[m] = fmaf(pm, v[n], v[m]);
+                v[n] = fmaf(qm, v[m], v[n]);
+                v[m] = fmaf(pm, v[n], v[m]);
+                g[m] = fmaf(pm, g[n], g[m]);
+                g[n] = fmaf(qm, g[m], g[n]);
+                g[m] = fmaf(pm, g[n], g[m]);
             });
-            const float sum = lane_sum<H>(contrib, lane);
+            float sum = lane_sum<H>(contrib, lane);
+            if ((flip >> my_pair) & 1u) sum = -sum;
             if (owner) unsafeAtomicAdd(gc + static_cast<int64_t>(r * D + K) * H + my_pair, sum);
+        });
+    }
+    // stored gradients carry the walk's final signs
+    if (as_ctab(bmodes)[c]) {
+        ctab_f sg = as_ctab(bsigns) + c * N;
+        StaticFor<0, N>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            g[i] *= sg[i];
         });
     }
 
@@ -208,7 +234,8 @@ hipError_t launch_bwd(const float* y, const float* gy, float* gx, float* gangles
     const int64_t groups = (l.max_tiles + kBwdWaves - 1) / kBwdWaves;
     const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
     hipLaunchKernelGGL((backward_kernel<D>), grid, dim3(64 * kBwdWaves), 0, stream, y, gy, gx,
-                       gangles, nblocks, rounds, l.max_tiles, p.tile_class, p.perm, p.trig);
+                       gangles, nblocks, rounds, l.max_tiles, p.tile_class, p.perm, p.bcoef,
+                       p.bflip, p.bsigns, p.bmodes);
     return hipGetLastError();
 }
 
@@ -219,7 +246,8 @@ hipError_t launch_backward(const float* y, const float* gy, float* gx, float* ga
                            int nclasses, const WsLayout& l, const WsPtrs& p,
                            hipStream_t stream) {
     hipLaunchKernelGGL(backward_prep_kernel, dim3(static_cast<unsigned>(nclasses)),
-                       dim3(kPrepThreads), 0, stream, angles, log2n, rounds, p.trig, gangles);
+                       dim3(kPrepThreads), 0, stream, angles, log2n, rounds, p.bcoef, p.bflip,
+                       p.bsigns, p.bmodes, gangles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nblocks == 0) return e;
     switch (log2n) {

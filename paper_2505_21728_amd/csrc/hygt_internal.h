@@ -46,7 +46,11 @@ struct WsLayout {
     size_t modes = 0;        // int32 [2][C] 1 = some output needs a final sign flip
     size_t coef = 0;         // float [2][C][P][N] per-pass multipliers (two per pair)
     size_t signs = 0;        // float [2][C][N] final sign (+1 / -1) of each output
-    size_t trig = 0;         // float [C][R*d][N] (cos, sin) per pair, forward order (backward)
+    // the backward's own inverse-direction tables, built from its angles:
+    size_t bcoef = 0;        // float [C][P][N] lifting multipliers, application order
+    size_t bflip = 0;        // uint32 [C][P] pairs whose stored signs differ, per pass
+    size_t bsigns = 0;       // float [C][N] final signs
+    size_t bmodes = 0;       // int32 [C] 1 = some final sign is -1
     size_t total = 0;
     int64_t nchunks = 0;
     int64_t chunk = 0;       // blocks per chunk (a multiple of 256)
@@ -86,7 +90,10 @@ inline WsLayout ws_layout(int64_t nblocks, int log2n, int rounds, int nclasses) 
     l.modes = take(2 * C * 4);
     l.coef = take(2 * C * static_cast<size_t>(l.passes) * l.n * 4);
     l.signs = take(2 * C * static_cast<size_t>(l.n) * 4);
-    l.trig = take(C * static_cast<size_t>(l.passes) * l.n * 4);
+    l.bcoef = take(C * static_cast<size_t>(l.passes) * l.n * 4);
+    l.bflip = take(C * static_cast<size_t>(l.passes) * 4);
+    l.bsigns = take(C * static_cast<size_t>(l.n) * 4);
+    l.bmodes = take(C * 4);
     l.total = off;
     return l;
 }
@@ -101,7 +108,10 @@ struct WsPtrs {
     int32_t* modes;
     float* coef;
     float* signs;
-    float* trig;
+    float* bcoef;
+    uint32_t* bflip;
+    float* bsigns;
+    int32_t* bmodes;
 };
 
 inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
@@ -115,7 +125,10 @@ inline WsPtrs ws_ptrs(void* ws, const WsLayout& l) {
     p.modes = reinterpret_cast<int32_t*>(b + l.modes);
     p.coef = reinterpret_cast<float*>(b + l.coef);
     p.signs = reinterpret_cast<float*>(b + l.signs);
-    p.trig = reinterpret_cast<float*>(b + l.trig);
+    p.bcoef = reinterpret_cast<float*>(b + l.bcoef);
+    p.bflip = reinterpret_cast<uint32_t*>(b + l.bflip);
+    p.bsigns = reinterpret_cast<float*>(b + l.bsigns);
+    p.bmodes = reinterpret_cast<int32_t*>(b + l.bmodes);
     return p;
 }
 

@@ -44,14 +44,22 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / den if den > 0 else np.linalg.norm(a)
 
 
-def _check_grads(gx, ga, gx_ref, ga_ref, cls, nclasses, what):
+def _check_grads(gx, ga, gx_ref, ga_ref, mass, cls, nclasses, what):
+    """dL/dx: relative L2 per block. dL/dangles: relative L2 over all angles,
+    and per angle an error within TOL_A of the summed magnitudes of the terms
+    behind it (a class's gradient is a sum of per-block terms of both signs,
+    and a floating-point sum's error is bounded against that mass, not against
+    the possibly much smaller result)."""
     eb = orc.rel_l2_per_block(gx, gx_ref)
     assert eb.max() <= TOL_X, f"{what}: dL/dx per-block {eb.max():.3e}"
     ea = _rel(ga, ga_ref)
     per_class = [_rel(ga[c], ga_ref[c]) for c in range(nclasses) if np.any(cls == c)]
+    err = np.abs(ga - ga_ref)
+    vs_mass = np.max(np.where(mass > 0, err / np.where(mass > 0, mass, 1.0), 0.0))
     _say(f"[gpu] {what}: dL/dx {eb.max():.2e}, dL/dangles global {ea:.2e}, "
-         f"worst class {max(per_class):.2e}")
-    assert ea <= TOL_A and max(per_class) <= TOL_A, f"{what}: dL/dangles {ea:.3e}"
+         f"worst class {max(per_class):.2e}, worst vs term mass {vs_mass:.2e}")
+    assert ea <= TOL_A, f"{what}: dL/dangles {ea:.3e}"
+    assert np.all(err <= TOL_A * mass), f"{what}: dL/dangles error {vs_mass:.3e} of the term mass"
     for c in range(nclasses):
         if not np.any(cls == c):
             assert np.all(ga[c] == 0), f"{what}: empty class {c} has a gradient"
@@ -66,8 +74,9 @@ def _run(x, cls, ang, dev):
     gy = orc.class_log_variance_grad(y64, cls, ang.shape[0]).astype(np.float32)
     gx, ga = plan.backward(y, _to(gy, dev), at)
     torch.cuda.synchronize()
-    gx_ref, ga_ref = orc.backward(y64, gy.astype(np.float64), cls, ang)
-    return gx.cpu().numpy().astype(np.float64), ga.cpu().numpy().astype(np.float64), gx_ref, ga_ref
+    gx_ref, ga_ref, mass = orc.backward(y64, gy.astype(np.float64), cls, ang, with_mass=True)
+    return (gx.cpu().numpy().astype(np.float64), ga.cpu().numpy().astype(np.float64), gx_ref,
+            ga_ref, mass)
 
 
 def test_backward_config4_small():
@@ -75,8 +84,11 @@ def test_backward_config4_small():
 
     dL/dangles: each term g_m y_n - g_n y_m carries a few FP32 rounding errors
     relative to |g||y|, recomputed inputs add a few ulps per pass walked
-    back, and each class sums ~234 such terms of both signs; measured errors
-    are 1e-7 here and at most 2.2e-6 over the size sweep, the bound is 1e-5."""
+    back, and each class sums ~234 such terms of both signs. The bound is
+    1e-5 relative over all angles, and per angle 1e-5 of the summed term
+    magnitudes: the size sweep's i.i.d. inputs give class gradients that
+    nearly cancel (for N = 2 up to ~1300 times below their term mass), where
+    a relative bound on the result would measure the cancellation."""
     dev = _dev()
     ang = synth.angles(35, 4, 6)
     x = synth.ar1_blocks(8191, 8, seed=31)
@@ -104,7 +116,7 @@ def test_backward_fd_256_blocks():
     ang = synth.angles(35, 4, 6)
     x = synth.ar1_blocks(256, 8, seed=5)
     cls = synth.classes(256, 35, seed=6)
-    _, ga, _, _ = _run(x, cls, ang, dev)
+    _, ga, _, _, _ = _run(x, cls, ang, dev)
     a64, x64 = ang.astype(np.float64), x.astype(np.float64)
 
     def loss(a):

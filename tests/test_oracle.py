@@ -706,3 +706,29 @@ def test_int_unmutated_harness_passes():
     m = _mutant_int()
     for pin in INT_PINS:
         pin(m)
+
+
+def test_backward_term_mass():
+    """The magnitude sums returned beside the angle gradient: never below the
+    gradient's magnitude (triangle inequality), equal to it when the terms of
+    an angle share one sign, and for N = 2 exactly |g_0 y_1| + |g_1 y_0|
+    summed over the blocks."""
+    rng = np.random.default_rng(61)
+    C, R, d = 3, 2, 3
+    ang = rng.uniform(-math.pi, math.pi, (C, R, d, 4))
+    y = rng.standard_normal((50, 8))
+    gy = rng.standard_normal((50, 8))
+    cls = rng.integers(0, C, 50)
+    gx, ga, mass = orc.backward(y, gy, cls, ang, with_mass=True)
+    gx2, ga2 = orc.backward(y, gy, cls, ang)
+    assert np.array_equal(gx, gx2) and np.array_equal(ga, ga2)
+    assert np.all(mass >= np.abs(ga) - 1e-12)
+    # N = 2, R = 1: the only pass walked sees y and gy themselves
+    y2 = np.array([[1.0, 2.0], [-3.0, 0.5]])
+    g2 = np.array([[0.5, -1.0], [2.0, 4.0]])
+    _, ga1, m1 = orc.backward(y2, g2, np.array([0, 0]), np.array([[[[0.3]]]]), with_mass=True)
+    assert m1[0, 0, 0, 0] == (0.5 * 2.0 + 1.0 * 1.0) + (2.0 * 0.5 + 4.0 * 3.0)
+    # one term per angle with g_m y_n >= 0 >= g_n y_m: no cancellation
+    _, ga3, m3 = orc.backward(np.array([[0.0, 1.0]]), np.array([[1.0, 0.0]]), None,
+                              np.array([[[[0.7]]]]), with_mass=True)
+    assert m3[0, 0, 0, 0] == abs(ga3[0, 0, 0, 0]) == 1.0
