@@ -202,10 +202,11 @@ int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks,
  *            overwritten; classes without blocks get zeros).
  * Nothing from the forward call is needed but y: each pass's inputs are
  * recovered from its outputs by the inverse rotation (eq. (9)). For one
- * rotation, dL/dtheta = g_m y_n - g_n y_m. The workspace must hold a plan for
- * these sizes, classes and angles (hygt_plan()); this call also writes a
- * (cos, sin) table into it, so it must not overlap other calls on the same
- * workspace. Alignment as for hygt_apply(); gx may be gy (in place) but not
+ * rotation, dL/dtheta = g_m y_n - g_n y_m. The workspace must hold a plan
+ * (hygt_plan()) for these sizes and classes; its block grouping is used, and
+ * this call builds its own inverse-direction multiplier table from `angles`
+ * in a separate part of the workspace, so it must not overlap other
+ * hygt_backward() calls on the same workspace. Alignment as for hygt_apply(); gx may be gy (in place) but not
  * y. log2n <= HYGT_BACKWARD_MAX_LOG2N. The per-class sums are FP32 atomic
  * additions, so their last bits can differ from run to run. */
 int hygt_backward(const float* y, const float* gy, float* gx, float* gangles, int64_t nblocks,
