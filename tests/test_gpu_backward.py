@@ -186,3 +186,40 @@ def test_backward_zero_gradient_and_in_place():
     gy_in = gy.clone()
     gx_in, _ = plan.backward(y, gy_in, at, gx=gy_in)
     assert torch.equal(gx_in, gx_out)
+
+
+def test_backward_full_size_sampled():
+    """The gradient step's launch at full size: 2^20 8x8 blocks, 35 classes,
+    R = 4. dL/dy is zero except on 2048 sampled blocks, so every class's
+    angle gradient is the sum over the sample alone, which the oracle
+    computes exactly; dL/dx must match the oracle on the sample and be
+    exactly zero everywhere else."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    nb, C = 1 << 20, 35
+    _say("[gpu] backward full size: generating inputs")
+    ang = synth.angles(C, 4, 6)
+    x = synth.ar1_blocks(nb, 8)
+    cls = synth.classes(nb, C)
+    at = _to(ang, dev)
+    plan = hygt.Plan(at, _to(cls, dev))
+    y = plan.forward(_to(x, dev))
+    sample = np.sort(np.random.default_rng(41).choice(nb, 2048, replace=False))
+    gs = np.random.default_rng(42).standard_normal((2048, 64)).astype(np.float32)
+    gy = torch.zeros_like(y)
+    st = torch.from_numpy(sample).to(dev)
+    gy[st] = _to(gs, dev)
+    gx, ga = plan.backward(y, gy, at)
+    torch.cuda.synchronize()
+    _say("[gpu] backward full size: comparing")
+    ys = y[st].cpu().numpy().astype(np.float64)
+    gx_ref, ga_ref, mass = orc.backward(ys, gs.astype(np.float64), cls[sample], ang,
+                                        with_mass=True)
+    gxs = gx[st].cpu().numpy().astype(np.float64)
+    assert orc.rel_l2_per_block(gxs, gx_ref).max() <= TOL_X
+    rest = torch.ones(nb, dtype=torch.bool, device=dev)
+    rest[st] = False
+    assert int(torch.count_nonzero(gx[rest])) == 0
+    ga = ga.cpu().numpy().astype(np.float64)
+    assert _rel(ga, ga_ref) <= TOL_A
+    assert np.all(np.abs(ga - ga_ref) <= TOL_A * mass)

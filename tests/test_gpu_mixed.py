@@ -160,3 +160,33 @@ def test_mixed_plan_with_empty_segment_and_class_counts():
     for i, (y, p) in enumerate(zip(mb.y, plain)):
         assert np.array_equal(y.cpu().numpy(), p), f"segment {i}"
     mb.check()
+
+
+def test_mixed_workload_full_size_sampled():
+    """The benchmark's mixed workload at full size: 2^18 4x4 blocks (R = 2),
+    2^17 8x8 and 2^15 16x16 (R = 4), 35 classes each, AR(1) residuals, one
+    fused plan and one launch with the autotuned shape; 1024 sampled blocks
+    of every segment against the oracle."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    spec = [(4, 2, 1 << 18), (6, 4, 1 << 17), (8, 4, 1 << 15)]
+    host, segs = [], []
+    for i, (d, r, nb) in enumerate(spec):
+        _say(f"[gpu] mixed full size: generating segment {i} (d={d}, {nb} blocks)")
+        ang = synth.angles(35, r, d, seed=1 + i)
+        x = synth.ar1_blocks(nb, 1 << (d // 2), seed=2 + i)
+        cls = synth.classes(nb, 35, seed=3 + i)
+        host.append((x, cls, ang))
+        segs.append((_to(x, dev), _to(cls, dev), _to(ang, dev)))
+    mb = hygt.MixedBatch(segs)
+    cfg, _ = mb.autotune(0)
+    mb.plan()
+    mb.apply(0, config=cfg)
+    torch.cuda.synchronize()
+    mb.check()
+    for i, ((x, cls, ang), y) in enumerate(zip(host, mb.y)):
+        _say(f"[gpu] mixed full size: comparing segment {i}")
+        sample = np.random.default_rng(50 + i).choice(x.shape[0], 1024, replace=False)
+        ys = y[torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
+        ref = orc.forward(x[sample], cls[sample], ang)
+        assert orc.rel_l2_per_block(ys, ref).max() <= 1e-5, f"segment {i}"

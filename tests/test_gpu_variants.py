@@ -238,3 +238,41 @@ def test_integer_plan_rejects_float_ops():
                             _to(np.zeros((2, 16), np.int32), dev))
     with pytest.raises(TypeError):
         hygt.Plan(_to(synth.angles(2, 2, 4), dev), _to(cls, dev), integer=True)
+
+
+def test_variants_full_size_sampled():
+    """The permutation pass and the integer transform in the benchmark's
+    launch configuration: 2^20 8x8 AR(1) blocks, 35 classes, R = 4. The
+    integer codes are the angles rounded to the 8-bit grid. 2048 sampled
+    blocks against the oracle: permuted forward and inverse within 1e-5,
+    integer forward and inverse bit for bit."""
+    import paper_2505_21728_amd as hygt
+    dev = _dev()
+    nb, C = 1 << 20, 35
+    _say("[gpu] variants full size: generating inputs")
+    ang = synth.angles(C, 4, 6)
+    x = synth.ar1_blocks(nb, 8)
+    cls = synth.classes(nb, C)
+    perm = _perms(C, 64, np.random.default_rng(61), identity_class=False)
+    sample = np.random.default_rng(62).choice(nb, 2048, replace=False)
+    st = torch.from_numpy(sample).to(dev)
+    xt, ct = _to(x, dev), _to(cls, dev)
+    plan = hygt.Plan(_to(ang, dev), ct)
+    yp = plan.apply_permuted(xt, hygt.HYGT_FORWARD, _to(perm, dev))
+    zp = plan.apply_permuted(yp, hygt.HYGT_INVERSE, _to(perm, dev))
+    torch.cuda.synchronize()
+    _say("[gpu] variants full size: permutation pass")
+    ref = orc.forward_permuted(x[sample], cls[sample], ang, perm)
+    _close(yp[st].cpu().numpy(), ref, "full-size permuted forward")
+    _close(zp[st].cpu().numpy(), x[sample].astype(np.float64), "full-size permuted round trip")
+    codes = orc.codes_from_angles(ang)
+    iplan = hygt.Plan(_to(codes, dev), ct, integer=True)
+    xi = x.astype(np.int32)
+    yi = iplan.forward(_to(xi, dev))
+    zi = iplan.inverse(yi)
+    torch.cuda.synchronize()
+    _say("[gpu] variants full size: integer transform")
+    yref = orc.forward_int(xi[sample], cls[sample], codes)
+    assert np.array_equal(yi[st].cpu().numpy().astype(np.int64), yref)
+    zref = orc.inverse_int(yref, cls[sample], codes)
+    assert np.array_equal(zi[st].cpu().numpy().astype(np.int64), zref)
