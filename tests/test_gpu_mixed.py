@@ -190,3 +190,26 @@ def test_mixed_workload_full_size_sampled():
         ys = y[torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
         ref = orc.forward(x[sample], cls[sample], ang)
         assert orc.rel_l2_per_block(ys, ref).max() <= 1e-5, f"segment {i}"
+
+
+def test_mixed_plan_many_classes():
+    """A segment with 4096 classes (the placing launch's LDS then exceeds
+    64 KB) beside an ordinary one, in one fused plan: each segment equals its
+    single-size result bit for bit."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    spec = [(4, 2, 4096, 20000), (6, 4, 35, 3000)]
+    segs, plain = [], []
+    for i, (d, r, c, nb) in enumerate(spec):
+        _say(f"[gpu] mixed many classes: segment {i} d={d} C={c} B={nb}")
+        ang = _to(synth.angles(c, r, d, seed=70 + i), dev)
+        x = _to(synth.gaussian_blocks(nb, 1 << d, seed=71 + i), dev)
+        cls = _to(synth.classes(nb, c, seed=72 + i), dev)
+        segs.append((x, cls, ang))
+        plain.append(hygt.Plan(ang, cls).forward(x).cpu().numpy())
+    mb = hygt.MixedBatch(segs)
+    mb.apply(0)
+    torch.cuda.synchronize()
+    for i, (y, p) in enumerate(zip(mb.y, plain)):
+        assert np.array_equal(y.cpu().numpy(), p), f"segment {i}"
+    mb.check()
