@@ -78,12 +78,18 @@ def _copy_calibration(torch, dev):
 
 
 def kernel_source_sha256() -> str:
+    """Hash of the rotation kernel's sources with // comments and layout
+    removed: any change to the code invalidates the recorded traffic, a
+    change to its comments does not."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        code = re.sub(r"//[^\n]*", "", text)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

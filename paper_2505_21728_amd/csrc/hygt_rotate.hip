@@ -386,8 +386,9 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
     });
 }
 
-// N >= 4: one tile per wavefront, or for N = 256 one tile per pair of
-// wavefronts (a workgroup), wavefront h holding half h of every block.
+// N >= 4: one tile per wavefront, or for N = 128 and N = 256 one tile per
+// workgroup of 2 or 4 wavefronts, wavefront q holding values 64q .. 64q+63
+// of every block.
 template <int D, int DIR, int RT>
 __global__ __launch_bounds__(64 * TileGeo<D>::WAVES)
 __attribute__((amdgpu_waves_per_eu(TileGeo<D>::OCC)))
