@@ -64,6 +64,11 @@ __all__ = [
     "backward",
     "angles_from_codes",
     "codes_from_angles",
+    "INT_FRAC_BITS",
+    "int_multipliers",
+    "forward_int",
+    "inverse_int",
+    "int_error_bound",
     "forward_permuted",
     "inverse_permuted",
     "variance_order",
