@@ -302,7 +302,7 @@ __device__ __forceinline__ void unpermute_row(float* v, float4* R, ctab_i perm, 
 // completed, and no other wavefront touches it, so the restrict qualifiers
 // (which let the per-tile class loads stay scalar) hold for every pair of
 // accesses that the compiler could reorder.
-template <int D, int DIR, int RT, bool PERM = false, bool INTG = false>
+template <int D, int DIR, int RT, bool PERM = false, bool INTG = false, bool TILE_LOAD = false>
 __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* __restrict__ y,
                                             int64_t nblocks, int rounds, int nclasses,
                                             int64_t t0, int c, int q,
@@ -326,7 +326,11 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
         // lanes without a block compute on whatever their registers hold and
         // store nothing
         blk[u] = c < 0 ? -1 : valid_block(perm[(t0 + u) * kTile + lane], nblocks);
-        load_row<D>(xh, blk[u], v[u]);
+        if constexpr (TILE_LOAD && !G::SPLIT) {
+            if (c >= 0) load_tile<D>(xh, blk[u], v[u], L, lane);
+        } else {
+            load_row<D>(xh, blk[u], v[u]);
+        }
     });
 
     // with the permutation pass, the inverse first puts the coefficients back
@@ -409,8 +413,8 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
     if (t0 >= max_tiles) return;  // all wavefronts of a split tile leave together
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;  // past the last tile
-    rotate_tile<D, DIR, RT>(x, y, nblocks, rounds, nclasses, t0, c, q, perm, modes, coef, signs,
-                            lds[wv], lds[0], lane);
+    rotate_tile<D, DIR, RT, false, false, true>(x, y, nblocks, rounds, nclasses, t0, c, q, perm,
+                                                modes, coef, signs, lds[wv], lds[0], lane);
 }
 
 // N <= 64 with the permutation pass: as rotate_kernel, with a 16 KB row area
@@ -429,8 +433,9 @@ __global__ __launch_bounds__(64 * kWaves) void rotate_perm_kernel(
     if (t0 >= max_tiles) return;
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;
-    rotate_tile<D, DIR, 0, true>(x, y, nblocks, rounds, nclasses, t0, c, 0, perm, modes, coef,
-                                 signs, lds[wv], lds[wv], lane, as_ctab(outperm));
+    rotate_tile<D, DIR, 0, true, false, true>(x, y, nblocks, rounds, nclasses, t0, c, 0, perm,
+                                              modes, coef, signs, lds[wv], lds[wv], lane,
+                                              as_ctab(outperm));
 }
 
 // Integer blocks, 4 <= N <= 64: as rotate_kernel with the integer passes;
