@@ -18,17 +18,22 @@
 // before them (inverse). The fused launch for batches of several block
 // sizes (mixed_kernel) runs the same tile body over one persistent grid.
 //
-// Memory. Each lane loads its own block (for N > 64, its share of the block)
-// straight into registers, N / 4 loads of 16 bytes all in flight at once, so
-// the first passes start on the chunks that arrive first. The way out goes
-// through LDS: each lane writes its row, and the transposed slots go out so
-// that each store instruction writes whole blocks (or whole 128-byte halves
-// of 8x8 blocks), 16 bytes per lane; an XOR swizzle of the 16-byte chunks in
-// LDS keeps the row writes on distinct banks. A tile goes out in parts of at
-// most 8 chunks per block, so a wavefront needs only 8 KB of LDS. Stores are
-// non-temporal. Measured on MI355X with cache-cold inputs, direct loads beat
-// a gather through LDS (global_load_lds_dwordx4) by 4 to 6 us per 2^20 8x8
-// blocks, and non-temporal stores beat ordinary ones by 14 us.
+// Memory. The single-size kernels with N <= 64 bring a tile in through LDS
+// by DMA: each global_load_lds_dwordx4 reads the chunks of several whole
+// blocks, and each lane then reads its own row from LDS; for N = 64 half of
+// every block comes that way and the other half by the lanes' own row
+// loads, all in flight at once (load_tile in hygt_tile.h). The fused mixed
+// kernel, and tiles of N > 64, load each lane's block (or share of it)
+// straight into registers. The way out goes through LDS: each lane writes
+// its row, and the transposed slots go out so that each store instruction
+// writes whole blocks (or whole 128-byte halves of 8x8 blocks), 16 bytes per
+// lane; an XOR swizzle of the 16-byte chunks in LDS keeps the row writes on
+// distinct banks. A tile goes out in parts of at most 8 chunks per block, so
+// a wavefront needs only 8 KB of LDS, which the loads reuse. Stores are
+// non-temporal. Measured on MI355X with cache-cold inputs (2^20 8x8 blocks):
+// the half-DMA load beat row loads of whole blocks by 3 to 4 us, while a
+// whole-tile DMA in two halves lost 2 us (two round trips); non-temporal
+// stores beat ordinary ones by 14 us.
 //
 // Scheduling. Each wavefront handles one tile, four per workgroup. The
 // lifting form needs no temporaries, so a wavefront fits in under 100 VGPRs
