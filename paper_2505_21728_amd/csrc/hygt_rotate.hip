@@ -423,18 +423,23 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
 }
 
 // N <= 64 with the permutation pass: as rotate_kernel, with a 16 KB row area
-// per wavefront for the permutation (the part staging reuses its start).
+// per wavefront for the permutation (the loads and the part staging reuse its
+// start). LDS bounds the residency here, so workgroups are of two
+// wavefronts: five of them (10 wavefronts) fit a compute unit's 160 KB at
+// N = 64, against two of four.
+constexpr int kPermWaves = 2;
+
 template <int D, int DIR>
-__global__ __launch_bounds__(64 * kWaves) void rotate_perm_kernel(
+__global__ __launch_bounds__(64 * kPermWaves) void rotate_perm_kernel(
     const float* __restrict__ x, float* __restrict__ y, int64_t nblocks, int rounds,
     int nclasses, int64_t max_tiles, const int32_t* __restrict__ tile_class,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ modes,
     const float* __restrict__ coef, const float* __restrict__ signs,
     const int32_t* __restrict__ outperm) {
-    __shared__ float4 lds[kWaves][64 * ((1 << D) / 4)];
+    __shared__ float4 lds[kPermWaves][64 * ((1 << D) / 4)];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    const int64_t t0 = (xcd_tile_group() * kPermWaves + wv) * kTilesPerWave;
     if (t0 >= max_tiles) return;
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;
@@ -705,9 +710,9 @@ template <int D, int DIR>
 hipError_t launch_perm_one(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
                            const int32_t* outperm, const WsLayout& l, const WsPtrs& p,
                            hipStream_t stream) {
-    const int64_t groups = (l.max_tiles + kWaves - 1) / kWaves;
+    const int64_t groups = (l.max_tiles + kPermWaves - 1) / kPermWaves;
     const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
-    hipLaunchKernelGGL((rotate_perm_kernel<D, DIR>), grid, dim3(64 * kWaves), 0, stream, x, y,
+    hipLaunchKernelGGL((rotate_perm_kernel<D, DIR>), grid, dim3(64 * kPermWaves), 0, stream, x, y,
                        nblocks, rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes,
                        p.coef, p.signs, outperm);
     return hipGetLastError();
