@@ -72,6 +72,7 @@ __global__ __launch_bounds__(64 * kDenseWaves) void dense_kernel(
 #pragma unroll
     for (int i = 0; i < kChunks; ++i)
         bb[i] = __builtin_amdgcn_ds_bpermute((4 * i + lane / 16) << 2, blk);
+    (void)x;  // read only by the device pass below
 #if defined(__HIP_DEVICE_COMPILE__)  // the LDS-DMA builtin exists only in the device pass
 #pragma unroll
     for (int i = 0; i < kChunks; ++i) {
