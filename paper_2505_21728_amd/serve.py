@@ -59,6 +59,7 @@ class _Slot:
     cls: dict
     workspace: object
     handle: int = 0           # the stream's HIP handle
+    start: object = None      # events of the batch in flight, reused batch after batch
     event: object = None
     requests: list = field(default_factory=list)
     busy: bool = False
@@ -99,12 +100,14 @@ class Server:
                      for d in self.sizes},
                 workspace=torch.empty(ws_bytes, dtype=torch.uint8, device=dev)))
             self.slots[-1].handle = int(self.slots[-1].stream.cuda_stream)
+            self.slots[-1].start = torch.cuda.Event(enable_timing=True)
+            self.slots[-1].event = torch.cuda.Event(enable_timing=True)
         self.ws_bytes = ws_bytes
         self._meta = {d: (int(self.tables[d].data_ptr()), int(self.tables[d].shape[1]),
                           int(self.tables[d].shape[0])) for d in self.sizes}
         self.queue = collections.deque()
         self.batches = 0
-        self.busy_batches = []    # (start_event, end_event) per batch, for device busy time
+        self.busy_s = 0.0         # summed device time of the finished batches
         self.dispatch_s = 0.0     # host time spent starting batches
         self.config = self._tune() if config is None else config
         # device time origin: host time t0 <-> event e0
@@ -152,6 +155,7 @@ class Server:
         for s in self.slots:
             if s.busy and s.event.query():
                 t = self._device_time(s.event)
+                self.busy_s += s.start.elapsed_time(s.event) / 1e3
                 for r in s.requests:
                     r.done = t
                 completed += len(s.requests)
@@ -181,8 +185,7 @@ class Server:
             return
         direct = len(taken) <= _abi.HYGT_MAX_SEGMENTS
         with torch.cuda.stream(s.stream):
-            start = torch.cuda.Event(enable_timing=True)
-            start.record(s.stream)
+            s.start.record(s.stream)
             for r, _ in taken:
                 if r.ready is not None:
                     s.stream.wait_event(r.ready)
@@ -193,9 +196,7 @@ class Server:
                                   r.nblocks, r.log2n) for r, _ in taken])
             else:
                 self._gathered(s, taken, used)
-            s.event = torch.cuda.Event(enable_timing=True)
             s.event.record(s.stream)
-        self.busy_batches.append((start, s.event))
         s.requests = [r for r, _ in taken]
         s.busy = True
         self.batches += 1
@@ -250,7 +251,7 @@ def run_poisson(server: Server, requests: list, rate: float, seed: int = 4) -> d
     t_end = max(r.done for r in requests)
     lat = np.array([r.done - r.arrival for r in requests]) * 1e3
     blocks = sum(r.nblocks for r in requests)
-    busy = sum(a.elapsed_time(b) for a, b in server.busy_batches) / 1e3
+    busy = server.busy_s
     return {"requests": len(requests), "blocks": blocks, "batches": server.batches,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
