@@ -24,7 +24,8 @@
  *     arrays of Fig. 5). There are R * N * log2n / 2 angles per class (Sec. IV).
  *   - The inverse applies the passes in reverse order with negated angles
  *     (eq. (6), eq. (9), Sec. IV); it equals the transpose.
- *   - The optional final permutation pass of Fig. 4 is not applied.
+ *   - The optional final permutation pass of Fig. 4 is applied only by
+ *     hygt_apply_perm(); the other entry points leave it out.
  *
  * Memory and ownership
  *   Every array argument is DEVICE memory owned by the caller. The library
@@ -61,7 +62,9 @@
  * Determinism
  *   Each block's result depends only on that block's values, its class and
  *   the angle table: it is bit-identical whatever the batch it is in, the
- *   batch order, or in-place versus out-of-place execution.
+ *   batch order, or in-place versus out-of-place execution. The one
+ *   exception is hygt_backward()'s per-class angle gradient, a sum of FP32
+ *   atomic additions whose order, and so whose last bits, vary.
  */
 #ifndef HYGT_H
 #define HYGT_H
