@@ -13,9 +13,16 @@ all: four times the 256 MB last-level cache of the MI355X, so every step
 reads its inputs from HBM rather than from a cache warmed by the step
 before.
 
+The timed steps are enqueued back to back on one stream (no events or host
+synchronisation inside), bracketed by device synchronisations; blocks/s is
+the batch size over the wall time per step.
+
 Prints one JSON line: blocks/s for forward + inverse, the roofline of the
-dominant kernel (the forward rotation, timed with HIP events on the stream it
-runs on), and the FP64 oracle timed on a bounded sample on the host.
+dominant kernel (the forward rotation: K launches back to back on the stream
+it runs on, between two HIP events, so that the average launch duration
+holds no host work), and the FP64 oracle timed on a bounded sample on the
+host. The other legs (dense transform, variants, gradient step, mixed sizes,
+serving) are reported beside it.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -109,6 +116,22 @@ def _measured_traffic():
     return int(val.group(1))
 
 
+def _avg_ms(torch, fn, steps):
+    """Average duration of fn(i), i < steps, enqueued back to back on the
+    current stream between two HIP events (no host work and no event inside
+    the timed launches)."""
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(steps):
+        fn(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def _klt_comparison(torch, hygt, at, cs, xs, steps):
     """The dense per-class transform (BF16 MFMA grouped GEMM) on the same
     blocks and classes, with M_c = T_c (forward) and T_c^T (inverse) of the
@@ -128,20 +151,8 @@ def _klt_comparison(torch, hygt, at, cs, xs, steps):
     for k in range(3):
         plans[k % RING].dense(xs[k % RING], mats, out=y)
         plans[k % RING].dense(y, mats_t, out=z)
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
-    torch.cuda.synchronize()
-    for i in range(steps):
-        plan = plans[i % RING]
-        ev[4 * i].record(stream)
-        plan.dense(xs[i % RING], mats, out=y)
-        ev[4 * i + 1].record(stream)
-        ev[4 * i + 2].record(stream)
-        plan.dense(y, mats_t, out=z)
-        ev[4 * i + 3].record(stream)
-    torch.cuda.synchronize()
-    fwd = sum(ev[4 * i].elapsed_time(ev[4 * i + 1]) for i in range(steps)) / steps
-    inv = sum(ev[4 * i + 2].elapsed_time(ev[4 * i + 3]) for i in range(steps)) / steps
+    fwd = _avg_ms(torch, lambda i: plans[i % RING].dense(xs[i % RING], mats, out=y), steps)
+    inv = _avg_ms(torch, lambda i: plans[i % RING].dense(xs[i % RING], mats_t, out=z), steps)
     launch_bytes = NBLOCKS * BYTES_PER_BLOCK
     return {"kernel": "dense_kernel (BF16 MFMA 16x16x32, FP32 accumulate)",
             "fwd_ms": fwd, "inv_ms": inv,
@@ -176,27 +187,16 @@ def _variants(torch, hygt, at, cs, xs, steps):
         for k in range(3):
             run_fwd(k)
             run_inv(k)
-        stream = torch.cuda.current_stream()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
-        torch.cuda.synchronize()
-        for i in range(steps):
-            ev[4 * i].record(stream)
-            run_fwd(i)
-            ev[4 * i + 1].record(stream)
-            ev[4 * i + 2].record(stream)
-            run_inv(i)
-            ev[4 * i + 3].record(stream)
-        torch.cuda.synchronize()
-        fwd = sum(ev[4 * i].elapsed_time(ev[4 * i + 1]) for i in range(steps)) / steps
-        inv = sum(ev[4 * i + 2].elapsed_time(ev[4 * i + 3]) for i in range(steps)) / steps
+        fwd = _avg_ms(torch, run_fwd, steps)
+        inv = _avg_ms(torch, run_inv, steps)
         return {"fwd_ms": fwd, "inv_ms": inv,
                 "fwd_gbps": NBLOCKS * BYTES_PER_BLOCK / (fwd / 1e3) / 1e9}
 
     perm_t = timed(
         lambda k: plans[k % RING].apply_permuted(xs[k % RING], hygt.HYGT_FORWARD, perm, out=y),
-        lambda k: plans[k % RING].apply_permuted(y, hygt.HYGT_INVERSE, perm, out=z))
+        lambda k: plans[k % RING].apply_permuted(xs[k % RING], hygt.HYGT_INVERSE, perm, out=z))
     int_t = timed(lambda k: iplans[k % RING].forward(xi[k % RING], out=yi),
-                  lambda k: iplans[k % RING].inverse(yi, out=zi))
+                  lambda k: iplans[k % RING].inverse(xi[k % RING], out=zi))
     return {"permutation_pass": dict(kernel="rotate_perm_kernel<6,*>", **perm_t),
             "integer": dict(kernel="rotate_int_kernel<6,*> (int32, 14-bit multipliers)",
                             **int_t)}
@@ -221,15 +221,8 @@ def _grad_step(torch, hygt, at, cs, xs, steps):
     ga = torch.empty_like(at)
     for k in range(2):
         plans[k % RING].backward(ys[k % RING], gys[k % RING], at, gx=gx, gangles=ga)
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
-    torch.cuda.synchronize()
-    for i in range(steps):
-        ev[2 * i].record(stream)
-        plans[i % RING].backward(ys[i % RING], gys[i % RING], at, gx=gx, gangles=ga)
-        ev[2 * i + 1].record(stream)
-    torch.cuda.synchronize()
-    ms = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)) / steps
+    ms = _avg_ms(torch, lambda i: plans[i % RING].backward(ys[i % RING], gys[i % RING], at,
+                                                           gx=gx, gangles=ga), steps)
     launch_bytes = NBLOCKS * (3 * 4 * N + 4)   # read y and dL/dy, write dL/dx, block ids
     return {"kernel": "backward_prep_kernel + backward_kernel<6>", "ms": ms,
             "gbps": launch_bytes / (ms / 1e3) / 1e9,
@@ -377,22 +370,13 @@ def _cpu_baseline(x, cls, ang, sample):
 
 
 def _copy_ceiling(torch, xs, out, steps):
-    """Cache-cold device-to-device copy of one batch (256 MiB), cycling over
-    the input ring like the timed steps: the practical HBM ceiling."""
-    stream = torch.cuda.current_stream()
+    """Cache-cold device-to-device copy of one batch (256 MiB) through
+    torch's copy (the runtime's blit kernel), cycling over the input ring like
+    the timed steps."""
     for k in range(3):
         out.copy_(xs[k % len(xs)])
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    torch.cuda.synchronize()
-    for i in range(steps):
-        ev[i][0].record(stream)
-        out.copy_(xs[i % len(xs)])
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    ms = sorted(a.elapsed_time(b) for a, b in ev)
-    med = ms[len(ms) // 2]
-    return {"median_ms": med, "gbps": 2 * out.numel() * 4 / (med / 1e3) / 1e9}
+    ms = _avg_ms(torch, lambda i: out.copy_(xs[i % len(xs)]), steps)
+    return {"ms": ms, "gbps": 2 * out.numel() * 4 / (ms / 1e3) / 1e9}
 
 
 def _pcts(vals):
@@ -434,53 +418,50 @@ def main():
     shift = NBLOCKS // RING + 12345
     xs = [torch.roll(x0, k * shift, 0).contiguous() for k in range(RING)]
     cs = [torch.roll(c0, k * shift, 0).contiguous() for k in range(RING)]
-    xt, ct = xs[0], cs[0]
     at = torch.from_numpy(ang).to(dev)
-    yt = torch.empty_like(xt)
-    zt = torch.empty_like(xt)
-    ws = torch.empty(hygt.workspace_bytes(NBLOCKS, LOG2N, ROUNDS, NCLASSES),
-                     dtype=torch.uint8, device=dev)
+    yt = torch.empty_like(xs[0])
+    zt = torch.empty_like(xs[0])
+    wsb = hygt.workspace_bytes(NBLOCKS, LOG2N, ROUNDS, NCLASSES)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    main = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    def run_steps(nsteps):
+        """nsteps steps, each the whole path on batch k: plan, forward, inverse,
+        enqueued back to back on one stream with no host synchronisation."""
+        p = None
+        for k in range(nsteps):
+            p = hygt.Plan(at, cs[k % RING], workspace=ws, stream=main)
+            p.forward(xs[k % RING], out=yt, stream=main)
+            p.inverse(yt, out=zt, stream=main)
+        return p
 
-    def step(k, events=None):
-        if events:
-            events[4].record(stream)
-        plan = hygt.Plan(at, cs[k % RING], workspace=ws)
-        if events:
-            events[0].record(stream)
-        plan.forward(xs[k % RING], out=yt)
-        if events:
-            events[1].record(stream)
-            events[2].record(stream)
-        plan.inverse(yt, out=zt)
-        if events:
-            events[3].record(stream)
-            events[5].record(stream)
-        return plan
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    plan = step(0)
-    plan.check()
-
+    run_steps(max(args.warmup, 1)).check()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i, ev[i])
+    run_steps(args.steps)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    fwd_all = [e[0].elapsed_time(e[1]) for e in ev]
-    inv_all = [e[2].elapsed_time(e[3]) for e in ev]
-    step_all = [e[4].elapsed_time(e[5]) for e in ev]
-    fwd_ms = sum(fwd_all) / args.steps
-    inv_ms = sum(inv_all) / args.steps
-    ms_per_step = 1e3 * elapsed / args.steps
+    ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
     value = NBLOCKS / (ms_per_step / 1e3)
+
+    # Kernel rooflines: the forward (and inverse) launches alone, back to back
+    # on the main stream over the input ring with a plan per batch, bracketed
+    # by two HIP events; the average launch duration includes no host work.
+    plans = [hygt.Plan(at, cs[k], stream=main) for k in range(RING)]
+    for k in range(RING):
+        plans[k].forward(xs[k], out=yt)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record(main)
+    for i in range(args.steps):
+        plans[i % RING].forward(xs[i % RING], out=yt, stream=main)
+    e1.record(main)
+    for i in range(args.steps):
+        plans[i % RING].inverse(xs[i % RING], out=zt, stream=main)
+    e2.record(main)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / args.steps
+    inv_ms = e1.elapsed_time(e2) / args.steps
     launch_bytes = NBLOCKS * BYTES_PER_BLOCK
     achieved = launch_bytes / (fwd_ms / 1e3) / 1e9
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
@@ -513,7 +494,6 @@ def main():
         "step_pct_peak": 100.0 * step_gbps / HBM_PEAK_GBPS,
         "fwd_ms": fwd_ms,
         "inv_ms": inv_ms,
-        "event_ms": {"step": _pcts(step_all), "fwd": _pcts(fwd_all), "inv": _pcts(inv_all)},
         "copy_ceiling": copy,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,

@@ -25,7 +25,13 @@ ARCH = "gfx950"
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written out
 # with fmaf, so no other contraction may change the rounding.
-# -packed-fp32-ops off: no v_pk_{add,mul,fma}_f32 are generated.
+# -target-feature -packed-fp32-ops: the device pass turns the packed FP32
+# instructions (v_pk_add_f32, v_pk_mul_f32, v_pk_fma_f32) off, so the compiler
+# cannot pair ordinary float operations into them (without it, the backward
+# kernels alone hold a few hundred). The host pass, which knows no such
+# feature, warns that it ignores it; that warning is filtered out below.
+# tests/test_build_isa.py reads the built code objects back and checks that
+# none of these instructions is present.
 COMMON_FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",

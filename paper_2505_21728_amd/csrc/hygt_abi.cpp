@@ -242,6 +242,7 @@ int mixed_plan_impl(const hygt_segment* segs, int nseg, void* ws, size_t ws_byte
         m.nchunks = l.nchunks;
         m.chunk = l.chunk;
         m.max_tiles = l.max_tiles;
+        m.interleave = l.interleave;
         m.count_begin = count_wgs;
         m.place_begin = place_wgs;
         m.log2n = g.log2n;

@@ -147,7 +147,7 @@ void backward_kernel(const float* __restrict__ y, const float* __restrict__ gy,
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = xcd_tile_group() * kBwdWaves + wv;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kBwdWaves + wv;
     if (t0 >= max_tiles) return;
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;
@@ -231,8 +231,7 @@ template <int D>
 hipError_t launch_bwd(const float* y, const float* gy, float* gx, float* gangles,
                       int64_t nblocks, int rounds, const WsLayout& l, const WsPtrs& p,
                       hipStream_t stream) {
-    const int64_t groups = (l.max_tiles + kBwdWaves - 1) / kBwdWaves;
-    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    const dim3 grid(static_cast<unsigned>((l.max_tiles + kBwdWaves - 1) / kBwdWaves));
     hipLaunchKernelGGL((backward_kernel<D>), grid, dim3(64 * kBwdWaves), 0, stream, y, gy, gx,
                        gangles, nblocks, rounds, l.max_tiles, p.tile_class, p.perm, p.bcoef,
                        p.bflip, p.bsigns, p.bmodes);

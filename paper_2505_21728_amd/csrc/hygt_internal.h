@@ -11,18 +11,17 @@ namespace hygt {
 
 // Blocks per tile: one wavefront lane per block.
 constexpr int kTile = 64;
-// Tiles per wavefront of the rotation kernel; the plan gives each class a
-// multiple of this many tiles so that a wavefront's tiles share one class.
-#ifndef HYGT_TILES_PER_WAVE
-#define HYGT_TILES_PER_WAVE 1
-#endif
-constexpr int kTilesPerWave = HYGT_TILES_PER_WAVE;
 // Chunks of consecutive blocks counted and placed by one plan workgroup each:
 // at least 4096 blocks, at most kMaxChunks chunks.
 constexpr int64_t kMinChunk = 4096;
 constexpr int64_t kMaxChunks = 1024;
 // Threads per plan workgroup (>= N/2 for the table builders, N <= 256).
 constexpr int kPlanThreads = 256;
+// The interleaved tile order (see WsLayout::interleave) is used up to this
+// many classes and table entries per chunk; each entry costs the placing
+// launch O(nclasses) work.
+constexpr int kInterleaveMaxClasses = 64;
+constexpr int64_t kInterleaveMaxEntries = 2048;
 // Hypercube dimensions kept inside one wavefront lane: a lane holds at most
 // 64 values, so for N = 128 (256) two (four) wavefronts share each tile,
 // wavefront q holding values 64q .. 64q+63 of every block, and the passes
@@ -55,6 +54,11 @@ struct WsLayout {
     int64_t nchunks = 0;
     int64_t chunk = 0;       // blocks per chunk (a multiple of 256)
     int64_t max_tiles = 0;
+    // Tile order of the plan: 0 = class by class; > 0 = the tiles of all
+    // classes interleaved by tile index (round i holds tile i of every class
+    // that has one), with room for this many (class, tile index) entries per
+    // chunk in the placing launch's table.
+    int64_t interleave = 0;
     int passes = 0;
     int n = 0;
 };
@@ -72,10 +76,14 @@ inline WsLayout ws_layout(int64_t nblocks, int log2n, int rounds, int nclasses) 
     l.chunk = static_cast<int64_t>(align_up(static_cast<size_t>((nblocks + nch - 1) / nch), 256));
     if (l.chunk < 256) l.chunk = 256;
     l.nchunks = (nblocks + l.chunk - 1) / l.chunk;
-    // Classes are grouped over the whole batch: each class's tile count is
-    // rounded up to a multiple of kTilesPerWave.
-    l.max_tiles = ((nblocks + kTile - 1) / kTile + static_cast<int64_t>(nclasses) * kTilesPerWave +
-                   kTilesPerWave - 1) / kTilesPerWave * kTilesPerWave;
+    // Classes are grouped over the whole batch: at most one partly filled
+    // tile per class.
+    l.max_tiles = (nblocks + kTile - 1) / kTile + static_cast<int64_t>(nclasses);
+    // A chunk's blocks of class c have consecutive ranks in the class, so they
+    // fall in at most cnt_c / 64 + 2 of its tiles.
+    const int64_t entries = l.chunk / kTile + 2 * static_cast<int64_t>(nclasses) + 1;
+    if (nclasses <= kInterleaveMaxClasses && entries <= kInterleaveMaxEntries)
+        l.interleave = entries;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -161,6 +169,7 @@ struct PlanSeg {
     int64_t max_tiles;
     int64_t count_begin;  // first workgroup of launch A (counting)
     int64_t place_begin;  // first workgroup of launch B (tables, then placing)
+    int64_t interleave;   // WsLayout::interleave
     int log2n;
     int rounds;
     int nclasses;

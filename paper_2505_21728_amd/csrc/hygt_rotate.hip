@@ -13,6 +13,14 @@
 // through double-buffered LDS areas in parts of 16 per lane and rotate with
 // (cos, sin) multipliers instead of the lifting steps.
 //
+// Multipliers. The class table is read in chunks of the multipliers of up to
+// 16 pairs, each chunk requested one chunk ahead of its use (TableStream in
+// hygt_tile.h), so that the scalar loads of a pass overlap the arithmetic of
+// the pass before. Measured on MI355X (2^20 8x8 blocks, R = 4), this took
+// the forward transform from 119 to 112 us with the tiles in class order, and
+// made the cost of switching class tables between neighbouring tiles
+// negligible.
+//
 // Variants. The permutation pass of Fig. 4 (N <= 64) reorders each lane's
 // row through a per-wavefront LDS row area after the passes (forward) or
 // before them (inverse). The fused launch for batches of several block
@@ -33,18 +41,20 @@
 // non-temporal. Measured on MI355X with cache-cold inputs (2^20 8x8 blocks):
 // the half-DMA load beat row loads of whole blocks by 3 to 4 us, while a
 // whole-tile DMA in two halves lost 2 us (two round trips); non-temporal
-// stores beat ordinary ones by 14 us.
+// stores beat ordinary ones by 14 us; stores of 64-byte pieces of blocks
+// instead of 128-byte halves were 30 us slower.
 //
-// Scheduling. Each wavefront handles one tile, four per workgroup. The
-// lifting form needs no temporaries, so a wavefront fits in under 100 VGPRs
-// and five wavefronts per SIMD stay resident: measured on MI355X, raising
-// residency from two to five wavefronts per SIMD cut the 8x8 forward
-// transform from 177 to 144 us, because loads, rotations and stores of
-// different tiles then overlap. Tiles are sorted by class (see
-// hygt_plan.hip) and each XCD walks its own contiguous share of the tile
-// list, so the wavefronts that share a scalar cache mostly read one class
-// table: measured on MI355X, the rotation slows by about a third once a
-// compute-unit pair's wavefronts touch more than about three tables.
+// Scheduling. Each wavefront handles one tile and is a workgroup of its own
+// (tiles of N >= 128: a workgroup of the tile's wavefronts), and workgroup w
+// takes tile w of the plan's list. The lifting form needs no temporaries, so
+// a wavefront fits in under 100 VGPRs and five wavefronts per SIMD stay
+// resident, which lets the loads, rotations and stores of different tiles
+// overlap. The plan lists the tiles of all classes interleaved by their
+// position in the batch (see hygt_plan.hip), so the tiles running at any
+// moment read and write one compact window of the arrays. Measured on
+// MI355X (2^20 8x8 blocks, R = 4, with the multiplier prefetch): 107 us
+// forward against 122 us with the tiles in class order, and 4 us more when
+// each XCD walked its own contiguous share of the list.
 //
 // Arithmetic. Each pair is rotated with the three in-place lifting steps
 // built by the plan (see hygt_plan.hip), and a class whose sign bookkeeping
@@ -61,53 +71,29 @@ namespace {
 
 using namespace tile;
 
-// The passes act on T blocks at once (one per tile of the wavefront, all of
-// one class): every multiplier fetched is used by T blocks.
-
-// One pass along hypercube dimension K: each pair (m, n) gets the lifting
-// steps a += p b, b += q a, a += p b, in place (three FMAs, no temporary).
-template <int D, int K, int T>
-__device__ __forceinline__ void pass_lift(float (&v)[T][1 << D], ctab_f cp) {
-    StaticFor<0, (1 << D) / 2>::run([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        constexpr int m = ins0(j, K);
-        constexpr int n = m + (1 << K);
-        const float p = cp[2 * j];
-        const float q = cp[2 * j + 1];
-        StaticFor<0, T>::run([&](auto uu) {
-            constexpr int u = decltype(uu)::value;
-            v[u][m] = fmaf(p, v[u][n], v[u][m]);
-            v[u][n] = fmaf(q, v[u][m], v[u][n]);
-            v[u][m] = fmaf(p, v[u][n], v[u][m]);
-        });
-    });
+// Floats of a multiplier chunk for pairs of N = 2^D values: the whole pass
+// for N < 32, else 16 pairs.
+template <int D>
+constexpr int chunk_floats() {
+    return (1 << D) < 32 ? (1 << D) : 32;
 }
 
-// R rounds of D passes in application order (forward: k = 0..D-1 in every
-// round; inverse: k = D-1..0), then the final signs. RT > 0 unrolls the
-// rounds at compile time (RT == R); RT == 0 loops over `rounds`.
-template <int D, int DIR, int RT, int T>
-__device__ __forceinline__ void run_passes(float (&v)[T][1 << D], ctab_f tbl, ctab_f sign,
-                                           int has_neg, int rounds) {
-    constexpr int N = 1 << D;
-    auto one_round = [&](int r) {
-        StaticFor<0, D>::run([&](auto kk) {
-            constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
-            pass_lift<D, K, T>(v, tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N);
-        });
-    };
-    if constexpr (RT > 0) {
-        StaticFor<0, RT>::run([&](auto rr) { one_round(decltype(rr)::value); });
-    } else {
-        for (int r = 0; r < rounds; ++r) one_round(r);
-    }
-    if (has_neg) {
-        StaticFor<0, N>::run([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            const float sg = sign[i];
-            StaticFor<0, T>::run([&](auto uu) { v[decltype(uu)::value][i] *= sg; });
-        });
-    }
+// Pairs H*CP .. H*CP+CP-1 of a pass along dimension K (CP = F/2 pairs of the
+// chunk m): the lifting steps a += p b, b += q a, a += p b in place (three
+// FMAs, no temporary).
+template <int D, int K, int H, int F>
+__device__ __forceinline__ void lift_chunk(float (&v)[1 << D], const Chunk<F>& m) {
+    StaticFor<0, F / 2>::run([&](auto jj) {
+        constexpr int jl = decltype(jj)::value;
+        constexpr int j = H * (F / 2) + jl;
+        constexpr int mi = ins0(j, K);
+        constexpr int ni = mi + (1 << K);
+        const float p = m.template get<2 * jl>();
+        const float q = m.template get<2 * jl + 1>();
+        v[mi] = fmaf(p, v[ni], v[mi]);
+        v[ni] = fmaf(q, v[mi], v[ni]);
+        v[mi] = fmaf(p, v[ni], v[mi]);
+    });
 }
 
 // Integer arithmetic (Fig. 6): the registers hold int32 values (as bit
@@ -125,39 +111,76 @@ __device__ __forceinline__ int mad24(int p, int q, int r) {
     return out;
 }
 
-template <int D, int K, int T>
-__device__ __forceinline__ void pass_int(float (&v)[T][1 << D], ctab_i cp, int half) {
-    StaticFor<0, (1 << D) / 2>::run([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        constexpr int m = ins0(j, K);
-        constexpr int n = m + (1 << K);
-        const int c = cp[2 * j];
-        const int s = cp[2 * j + 1];
-        const int ns = -s;
-        StaticFor<0, T>::run([&](auto uu) {
-            constexpr int u = decltype(uu)::value;
-            const int a = __float_as_int(v[u][m]);
-            const int b = __float_as_int(v[u][n]);
-            const int ym = mad24(c, a, mad24(s, b, half)) >> kIntFracBits;
-            const int yn = mad24(c, b, mad24(ns, a, half)) >> kIntFracBits;
-            v[u][m] = __int_as_float(ym);
-            v[u][n] = __int_as_float(yn);
-        });
+template <int D, int K, int H, int F>
+__device__ __forceinline__ void int_chunk(float (&v)[1 << D], const Chunk<F>& m, int half) {
+    StaticFor<0, F / 2>::run([&](auto jj) {
+        constexpr int jl = decltype(jj)::value;
+        constexpr int j = H * (F / 2) + jl;
+        constexpr int mi = ins0(j, K);
+        constexpr int ni = mi + (1 << K);
+        const int c = __float_as_int(m.template get<2 * jl>());
+        const int s = __float_as_int(m.template get<2 * jl + 1>());
+        const int a = __float_as_int(v[mi]);
+        const int b = __float_as_int(v[ni]);
+        const int ym = mad24(c, a, mad24(s, b, half)) >> kIntFracBits;
+        const int yn = mad24(c, b, mad24(-s, a, half)) >> kIntFracBits;
+        v[mi] = __int_as_float(ym);
+        v[ni] = __int_as_float(yn);
     });
 }
 
-template <int D, int DIR, int T>
-__device__ __forceinline__ void run_passes_int(float (&v)[T][1 << D], ctab_i tbl, int rounds) {
+// R rounds of D passes in application order (forward: k = 0..D-1 in every
+// round; inverse: k = D-1..0), chunk by chunk from the table stream; pass p
+// of the table (application order) is at p * N. RT > 0 unrolls the rounds at
+// compile time (RT == R); RT == 0 loops over `rounds`. INTG selects the
+// integer butterflies. The prefetch after the last chunk of the last round
+// repeats that round's first chunk.
+template <int D, int DIR, int RT, bool INTG>
+__device__ __forceinline__ void run_rounds(float (&v)[1 << D], ctab_f tbl, int rounds) {
     constexpr int N = 1 << D;
-    // the rounding constant, once in a VGPR (an instruction may read only
-    // one scalar operand, and the multiplier is that one)
-    int half = 1 << (kIntFracBits - 1);
-    asm volatile("" : "+v"(half));
-    for (int r = 0; r < rounds; ++r) {
-        StaticFor<0, D>::run([&](auto kk) {
-            constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
-            pass_int<D, K, T>(v, tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N,
-                              half);
+    constexpr int F = chunk_floats<D>();
+    constexpr int CPP = N / F;    // chunks per pass
+    constexpr int CPR = D * CPP;  // chunks per round
+    int half = 0;
+    if constexpr (INTG) {
+        // the rounding constant, once in a VGPR (an instruction may read only
+        // one scalar operand, and the multiplier is that one)
+        half = 1 << (kIntFracBits - 1);
+        asm volatile("" : "+v"(half));
+    }
+    TableStream<F> ts;
+    ts.begin(tbl, 0);
+    auto one_round = [&](int64_t r, int64_t rnext) {
+        StaticFor<0, CPR>::run([&](auto ee) {
+            constexpr int e = decltype(ee)::value;
+            constexpr int kk = e / CPP;
+            constexpr int H = e % CPP;
+            constexpr int K = DIR == 0 ? kk : D - 1 - kk;
+            const int64_t nxt = e + 1 < CPR ? r * (D * N) + (e + 1) * F : rnext * (D * N);
+            const Chunk<F> m = ts.next(nxt);
+            if constexpr (INTG)
+                int_chunk<D, K, H, F>(v, m, half);
+            else
+                lift_chunk<D, K, H, F>(v, m);
+        });
+    };
+    if constexpr (RT > 0) {
+        StaticFor<0, RT>::run([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            one_round(r, r + 1 < RT ? r + 1 : r);
+        });
+    } else {
+        for (int r = 0; r < rounds; ++r) one_round(r, r + 1 < rounds ? r + 1 : r);
+    }
+}
+
+// The final signs of a class whose sign bookkeeping left negative outputs.
+template <int V>
+__device__ __forceinline__ void apply_signs(float (&v)[V], ctab_f sign, int has_neg) {
+    if (has_neg) {
+        StaticFor<0, V>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            v[i] *= sign[i];
         });
     }
 }
@@ -166,19 +189,21 @@ __device__ __forceinline__ void run_passes_int(float (&v)[T][1 << D], ctab_i tbl
 // 64q + i, bit K - 6 of q clear) with value i of wavefront q | 2^(K-6). The
 // two swap their values through LDS, 16 per lane at a time, and each
 // computes its own outputs: y_m = c x_m + s x_n on the lower wavefront,
-// y_n = c x_n - s x_m on the upper one, with (c, s) = cp[2i], cp[2i + 1]
-// (cp already offset to the wavefront pair's first pair). `xo` is this
-// wavefront's exchange area and `xp` the partner's, each two buffers of
-// [4][64] float4; part g uses buffer g % 2, so the barrier of part g + 1 also
-// guarantees that both wavefronts have read part g before either overwrites
-// its buffer. Every wavefront of the workgroup passes the same barriers.
-template <int V>
-__device__ __forceinline__ void cross_pass(float (&v)[V], ctab_f cp,
-                                           unsigned hbit, float4* xo, const float4* xp,
-                                           int lane) {
-    StaticFor<0, V / 16>::run([&](auto gg) {
+// y_n = c x_n - s x_m on the upper one, with (c, s) of pair i the two floats
+// at 2i of the wavefront pair's part of the pass (128 floats from `off`, in
+// four chunks of 16 pairs). `xo` is this wavefront's exchange area and `xp`
+// the partner's, each two buffers of [4][64] float4; part g uses buffer
+// g % 2, so the barrier of part g + 1 also guarantees that both wavefronts
+// have read part g before either overwrites its buffer. Every wavefront of
+// the workgroup passes the same barriers. `after` is the table offset of the
+// chunk that follows the pass.
+__device__ __forceinline__ void cross_pass(float (&v)[64], TableStream<32>& ts, int64_t off,
+                                           int64_t after, unsigned hbit, float4* xo,
+                                           const float4* xp, int lane) {
+    StaticFor<0, 4>::run([&](auto gg) {
         constexpr int g = decltype(gg)::value;
         constexpr int buf = g & 1;
+        const Chunk<32> m = ts.next(g + 1 < 4 ? off + 32 * (g + 1) : after);
         StaticFor<0, 4>::run([&](auto qq) {
             constexpr int q = decltype(qq)::value;
             constexpr int e = 16 * g + 4 * q;
@@ -197,8 +222,8 @@ __device__ __forceinline__ void cross_pass(float (&v)[V], ctab_f cp,
         StaticFor<0, 16>::run([&](auto tt) {
             constexpr int t = decltype(tt)::value;
             constexpr int j = 16 * g + t;
-            const float c = cp[2 * j];
-            const float sn = cp[2 * j + 1];
+            const float c = m.template get<2 * t>();
+            const float sn = m.template get<2 * t + 1>();
             // -s on the upper wavefront: a sign-bit flip of a wave-uniform value
             const float sg = __uint_as_float(__float_as_uint(sn) ^ hbit);
             v[j] = fmaf(sg, w[t], c * v[j]);
@@ -208,38 +233,51 @@ __device__ __forceinline__ void cross_pass(float (&v)[V], ctab_f cp,
 
 // N >= 128, wavefront q of a tile's 2^(D-6) wavefronts: R rounds of D
 // passes in application order. Passes along bits 0..5 act on the lane's 64
-// values with the multipliers of pairs 32q .. 32q + 31 of the pass; passes
-// along bits 6, 7 go through cross_pass with the partner wavefront
-// q ^ 2^(K-6), whose pairs start at 64 * (q without bit K-6). Then the final
-// signs of elements 64q .. 64q + 63. The tile's wavefronts have consecutive
-// LDS areas of 512 float4 starting at `area0`.
+// values with the multipliers of pairs 32q .. 32q + 31 of the pass (table
+// floats 64q .. 64q + 63 of the pass, two chunks); passes along bits 6, 7 go
+// through cross_pass with the partner wavefront q ^ 2^(K-6), whose pairs
+// start at 64 * (q without bit K-6). Then the final signs of elements
+// 64q .. 64q + 63. The tile's wavefronts have consecutive LDS areas of 512
+// float4 starting at `area0`.
 template <int D, int DIR>
-__device__ __forceinline__ void run_passes_split(float (&v)[1][64], ctab_f tbl, ctab_f sign,
-                                                 int has_neg,
-                                                 int rounds, int q, float4* area0,
+__device__ __forceinline__ void run_passes_split(float (&v)[64], ctab_f tbl, ctab_f sign,
+                                                 int has_neg, int rounds, int q, float4* area0,
                                                  int lane) {
     constexpr int N = 1 << D;
     constexpr int V = 64;
+    // table offset of the first chunk of pass kk (application order) of round r
+    auto first = [&](int64_t r, int kk) -> int64_t {
+        const int K = DIR == 0 ? kk : D - 1 - kk;
+        int64_t off = (r * D + kk) * N;
+        if (K >= kLaneBits) {
+            const int b = K - kLaneBits;
+            const int qq = ((q >> (b + 1)) << b) | (q & ((1 << b) - 1));
+            return off + 2 * V * qq;
+        }
+        return off + q * V;
+    };
+    TableStream<32> ts;
+    ts.begin(tbl, first(0, 0));
     for (int r = 0; r < rounds; ++r) {
+        const int64_t rnext = r + 1 < rounds ? r + 1 : r;
         StaticFor<0, D>::run([&](auto kk) {
-            constexpr int K = DIR == 0 ? decltype(kk)::value : D - 1 - decltype(kk)::value;
-            ctab_f cp = tbl + static_cast<size_t>(r * D + decltype(kk)::value) * N;
+            constexpr int k = decltype(kk)::value;
+            constexpr int K = DIR == 0 ? k : D - 1 - k;
+            const int64_t off = first(r, k);
+            const int64_t after = k + 1 < D ? first(r, k + 1) : first(rnext, 0);
             if constexpr (K >= kLaneBits) {
                 constexpr int b = K - kLaneBits;
-                const int qq = ((q >> (b + 1)) << b) | (q & ((1 << b) - 1));
-                cross_pass<V>(v[0], cp + 2 * V * qq, static_cast<unsigned>((q >> b) & 1) << 31,
-                              area0 + 512 * q, area0 + 512 * (q ^ (1 << b)), lane);
+                cross_pass(v, ts, off, after, static_cast<unsigned>((q >> b) & 1) << 31,
+                           area0 + 512 * q, area0 + 512 * (q ^ (1 << b)), lane);
             } else {
-                pass_lift<kLaneBits, K, 1>(v, cp + q * V);
+                const Chunk<32> m0 = ts.next(off + 32);
+                lift_chunk<kLaneBits, K, 0, 32>(v, m0);
+                const Chunk<32> m1 = ts.next(after);
+                lift_chunk<kLaneBits, K, 1, 32>(v, m1);
             }
         });
     }
-    if (has_neg) {
-        StaticFor<0, V>::run([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            v[0][i] *= sign[q * V + i];
-        });
-    }
+    apply_signs<V>(v, sign + q * V, has_neg);
 }
 
 // Permutation pass (Fig. 4), N <= 64, through this wavefront's row area R of
@@ -320,84 +358,57 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
     using G = TileGeo<D>;
     constexpr int N = G::N;
     constexpr int CHP = G::CHP;
-    constexpr int T = G::SPLIT ? 1 : kTilesPerWave;
     static_assert(!G::SPLIT || kTile * CHP == 512, "split tiles use areas of 512 float4");
     const float* xh = x + q * G::V;
     float* yh = y + q * G::V;
-    int blk[T];
-    float v[T][G::V];
-    StaticFor<0, T>::run([&](auto uu) {
-        constexpr int u = decltype(uu)::value;
-        // lanes without a block compute on whatever their registers hold and
-        // store nothing
-        blk[u] = c < 0 ? -1 : valid_block(perm[(t0 + u) * kTile + lane], nblocks);
-        if constexpr (TILE_LOAD && !G::SPLIT) {
-            if (c >= 0) load_tile<D>(xh, blk[u], v[u], L, lane);
-        } else {
-            load_row<D>(xh, blk[u], v[u]);
-        }
-    });
+    // lanes without a block compute on whatever their registers hold and
+    // store nothing
+    const int blk = c < 0 ? -1 : valid_block(perm[t0 * kTile + lane], nblocks);
+    float v[G::V];
+    if constexpr (TILE_LOAD && !G::SPLIT) {
+        if (c >= 0) load_tile<D>(xh, blk, v, L, lane);
+    } else {
+        load_row<D>(xh, blk, v);
+    }
 
     // with the permutation pass, the inverse first puts the coefficients back
     // in transform order (the row area is the staging area, 16 KB per wave)
-    if constexpr (PERM && DIR == 1)
-        StaticFor<0, T>::run([&](auto uu) {
-            unpermute_row<D>(v[decltype(uu)::value], L, outperm + c * N, lane);
-        });
+    if constexpr (PERM && DIR == 1) unpermute_row<D>(v, L, outperm + c * N, lane);
     const size_t passes = static_cast<size_t>(rounds) * D;
     const size_t table = static_cast<size_t>(DIR) * nclasses + (c < 0 ? 0 : c);
-    // Touch every 128-byte line of the class's multiplier table once, spread
-    // over the lanes, so that the whole table is on its way into L2 before
-    // the passes' scalar loads ask for it line by line. It matters when a
-    // launch has few tiles per class and large tables (N = 256: 32 KB per
-    // class and direction, far beyond the scalar cache), where each pass
-    // would otherwise wait for memory in turn.
-    float touch = 0.0f;
-    {
-        ctab_f tb = as_ctab(coef) + table * passes * N;
-        const int lines = static_cast<int>((passes * N * sizeof(float) + 127) / 128);
-        for (int i = lane; i < lines; i += 64) touch += tb[i * 32];
-    }
+    ctab_f tbl = as_ctab(coef) + table * passes * N;
     if constexpr (G::SPLIT) {
-        run_passes_split<D, DIR>(v, as_ctab(coef) + table * passes * N, as_ctab(signs) + table * N,
-                                 as_ctab(modes)[table], rounds, q, area0, lane);
+        run_passes_split<D, DIR>(v, tbl, as_ctab(signs) + table * N, as_ctab(modes)[table],
+                                 rounds, q, area0, lane);
         // The partners' last reads of this wavefront's exchange area come
         // before the stores below reuse it for staging.
         __syncthreads();
     } else if constexpr (INTG) {
-        run_passes_int<D, DIR, T>(
-            v, as_ctab(reinterpret_cast<const int32_t*>(coef)) + table * passes * N, rounds);
+        run_rounds<D, DIR, 0, true>(v, tbl, rounds);
     } else {
-        run_passes<D, DIR, RT, T>(v, as_ctab(coef) + table * passes * N,
-                                  as_ctab(signs) + table * N, as_ctab(modes)[table], rounds);
-        if constexpr (PERM && DIR == 0)
-            StaticFor<0, T>::run([&](auto uu) {
-                permute_row<D>(v[decltype(uu)::value], L, outperm + c * N, lane);
-            });
+        run_rounds<D, DIR, RT, false>(v, tbl, rounds);
+        apply_signs<N>(v, as_ctab(signs) + table * N, as_ctab(modes)[table]);
+        if constexpr (PERM && DIR == 0) permute_row<D>(v, L, outperm + c * N, lane);
     }
 
     // Addresses for the way out are derived again from the block ids and the
     // lane index, made opaque here so that the compiler does not keep the
-    // ones of the way in alive (in registers) across the passes. The table
-    // touches are consumed here too, so that they are not dropped.
+    // ones of the way in alive (in registers) across the passes.
     int lane2 = lane;
-    asm volatile("" : "+v"(lane2) : "v"(touch));
+    asm volatile("" : "+v"(lane2));
     const int sw2 = swz<CHP>(lane2);
-    StaticFor<0, T>::run([&](auto uu) {
-        constexpr int u = decltype(uu)::value;
-        int b = blk[u];
-        asm volatile("" : "+v"(b));
-        int bb[CHP];
-        instr_blocks<D>(bb, b, lane2);
-        StaticFor<0, G::PARTS>::run([&](auto pp) {
-            store_part<D, decltype(pp)::value>(yh, L, bb, v[u], lane2, sw2);
-        });
+    int b = blk;
+    asm volatile("" : "+v"(b));
+    int bb[CHP];
+    instr_blocks<D>(bb, b, lane2);
+    StaticFor<0, G::PARTS>::run([&](auto pp) {
+        store_part<D, decltype(pp)::value>(yh, L, bb, v, lane2, sw2);
     });
 }
 
-// N >= 4: one tile per wavefront, or for N = 128 and N = 256 one tile per
-// workgroup of 2 or 4 wavefronts, wavefront q holding values 64q .. 64q+63
-// of every block.
+// N >= 4: one tile per wavefront and workgroup, or for N = 128 and N = 256
+// one tile per workgroup of 2 or 4 wavefronts, wavefront q holding values
+// 64q .. 64q+63 of every block. Workgroup w takes tile w of the list.
 template <int D, int DIR, int RT>
 __global__ __launch_bounds__(64 * TileGeo<D>::WAVES)
 __attribute__((amdgpu_waves_per_eu(TileGeo<D>::OCC)))
@@ -412,9 +423,8 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = G::SPLIT ? wv : 0;  // share of every block held by this wavefront
-    // This wavefront's tiles; the plan gives them one class.
-    const int64_t t0 =
-        G::SPLIT ? xcd_tile_group() : (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    const int64_t t0 = G::SPLIT ? static_cast<int64_t>(blockIdx.x)
+                                : static_cast<int64_t>(blockIdx.x) * kWaves + wv;
     if (t0 >= max_tiles) return;  // all wavefronts of a split tile leave together
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;  // past the last tile
@@ -424,10 +434,9 @@ void rotate_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n
 
 // N <= 64 with the permutation pass: as rotate_kernel, with a 16 KB row area
 // per wavefront for the permutation (the loads and the part staging reuse its
-// start). LDS bounds the residency here, so workgroups are of two
-// wavefronts: five of them (10 wavefronts) fit a compute unit's 160 KB at
-// N = 64, against two of four.
-constexpr int kPermWaves = 2;
+// start). LDS bounds the residency here: ten wavefronts fit a compute unit's
+// 160 KB at N = 64.
+constexpr int kPermWaves = 1;
 
 template <int D, int DIR>
 __global__ __launch_bounds__(64 * kPermWaves) void rotate_perm_kernel(
@@ -439,7 +448,7 @@ __global__ __launch_bounds__(64 * kPermWaves) void rotate_perm_kernel(
     __shared__ float4 lds[kPermWaves][64 * ((1 << D) / 4)];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = (xcd_tile_group() * kPermWaves + wv) * kTilesPerWave;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kPermWaves + wv;
     if (t0 >= max_tiles) return;
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;
@@ -460,7 +469,7 @@ __global__ __launch_bounds__(64 * kWaves) void rotate_int_kernel(
     __shared__ float4 lds[kWaves][kTile * G::CHP];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kWaves + wv;
     if (t0 >= max_tiles) return;
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;
@@ -477,30 +486,27 @@ __global__ __launch_bounds__(64 * kWaves) void rotate_kernel_n2(
     const float* __restrict__ coef, const float* __restrict__ signs) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = (xcd_tile_group() * kWaves + wv) * kTilesPerWave;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kWaves + wv;
     if (t0 >= max_tiles) return;
     const int c = __builtin_amdgcn_readfirstlane(tile_class[t0]);
     if (c < 0) return;
     const size_t table = static_cast<size_t>(DIR) * nclasses + c;
-    for (int u = 0; u < kTilesPerWave; ++u) {
-        const int blk = valid_block(perm[(t0 + u) * kTile + lane], nblocks);
-        if (blk < 0) continue;
-        const float2 in = *reinterpret_cast<const float2*>(x + static_cast<int64_t>(blk) * 2);
-        float v[1][2] = {{in.x, in.y}};
-        run_passes<1, DIR, 0, 1>(v, as_ctab(coef) + table * rounds * 2, as_ctab(signs) + table * 2,
-                                 as_ctab(modes)[table], rounds);
-        *reinterpret_cast<float2*>(y + static_cast<int64_t>(blk) * 2) =
-            make_float2(v[0][0], v[0][1]);
-    }
+    const int blk = valid_block(perm[t0 * kTile + lane], nblocks);
+    float2 in = make_float2(0.0f, 0.0f);
+    if (blk >= 0) in = *reinterpret_cast<const float2*>(x + static_cast<int64_t>(blk) * 2);
+    float v[2] = {in.x, in.y};
+    run_rounds<1, DIR, 0, false>(v, as_ctab(coef) + table * rounds * 2, rounds);
+    apply_signs<2>(v, as_ctab(signs) + table * 2, as_ctab(modes)[table]);
+    if (blk >= 0)
+        *reinterpret_cast<float2*>(y + static_cast<int64_t>(blk) * 2) = make_float2(v[0], v[1]);
 }
 
 template <int D, int DIR, int RT>
 hipError_t launch_one(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
                       const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
     using G = TileGeo<D>;
-    const int64_t per_group = G::SPLIT ? 1 : static_cast<int64_t>(kWaves) * kTilesPerWave;
-    const int64_t groups = (l.max_tiles + per_group - 1) / per_group;
-    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    const int64_t per_group = G::SPLIT ? 1 : static_cast<int64_t>(kWaves);
+    const dim3 grid(static_cast<unsigned>((l.max_tiles + per_group - 1) / per_group));
     const dim3 block(D == 1 ? 64 * kWaves : 64 * G::WAVES);
     if constexpr (D == 1)
         hipLaunchKernelGGL((rotate_kernel_n2<DIR>), grid, block, 0, stream, x, y, nblocks,
@@ -710,8 +716,7 @@ template <int D, int DIR>
 hipError_t launch_perm_one(const float* x, float* y, int64_t nblocks, int rounds, int nclasses,
                            const int32_t* outperm, const WsLayout& l, const WsPtrs& p,
                            hipStream_t stream) {
-    const int64_t groups = (l.max_tiles + kPermWaves - 1) / kPermWaves;
-    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    const dim3 grid(static_cast<unsigned>((l.max_tiles + kPermWaves - 1) / kPermWaves));
     hipLaunchKernelGGL((rotate_perm_kernel<D, DIR>), grid, dim3(64 * kPermWaves), 0, stream, x, y,
                        nblocks, rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes,
                        p.coef, p.signs, outperm);
@@ -737,8 +742,7 @@ namespace {
 template <int D, int DIR>
 hipError_t launch_int_one(const int32_t* x, int32_t* y, int64_t nblocks, int rounds,
                           int nclasses, const WsLayout& l, const WsPtrs& p, hipStream_t stream) {
-    const int64_t groups = (l.max_tiles + kWaves - 1) / kWaves;
-    const dim3 grid(static_cast<unsigned>((groups + kXcds - 1) / kXcds * kXcds));
+    const dim3 grid(static_cast<unsigned>((l.max_tiles + kWaves - 1) / kWaves));
     hipLaunchKernelGGL((rotate_int_kernel<D, DIR>), grid, dim3(64 * kWaves), 0, stream,
                        reinterpret_cast<const float*>(x), reinterpret_cast<float*>(y), nblocks,
                        rounds, nclasses, l.max_tiles, p.tile_class, p.perm, p.modes, p.coef,

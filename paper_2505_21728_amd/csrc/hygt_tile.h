@@ -9,8 +9,10 @@
 namespace hygt {
 namespace tile {
 
-// Wavefronts (tiles) per workgroup of the rotation kernels.
-constexpr int kWaves = 4;
+// Wavefronts (tiles) per workgroup of the single-size rotation kernels for
+// N <= 64: one, so that every tile is dispatched on its own and a compute
+// unit's wavefronts start and finish independently.
+constexpr int kWaves = 1;
 // Accelerator complex dies (XCDs) that workgroups are dispatched over.
 constexpr int kXcds = 8;
 // Register budget of the rotation kernels: resident wavefronts per SIMD (a
@@ -221,16 +223,56 @@ __device__ __forceinline__ void store_part(float* __restrict__ y, float4* L, con
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// Tiles of workgroup w: workgroups are dispatched round-robin over the
-// XCDs (w mod 8), so workgroup w takes the (w / 8)-th group of tiles of
-// XCD (w mod 8)'s contiguous share of the class-sorted tile list. The waves
-// that share an XCD's scalar caches then work on one or two classes at a
-// time. The grid is a multiple of 8 workgroups.
-__device__ __forceinline__ int64_t xcd_tile_group() {
-    const int64_t w = blockIdx.x;
-    const int64_t per_xcd = gridDim.x / kXcds;
-    return (w % kXcds) * per_xcd + w / kXcds;
-}
+// Class tables (multipliers) read through the scalar cache one chunk ahead.
+//
+// A chunk is F consecutive floats of a table (F = 2, 4, 8, 16 or 32: the
+// multipliers of up to 16 pairs), held in one or two SGPR vectors. Left to
+// itself the compiler issues each chunk's scalar loads right before the
+// arithmetic that needs them and waits for them there, so every chunk costs a
+// full scalar-cache (or L2) round trip that only other wavefronts can hide.
+// The stream below requests chunk e + 1 while chunk e is used. next() first
+// passes the current chunk to an empty asm statement that also rewrites the
+// table pointer: the compiler must wait for that chunk there (when it is the
+// only scalar load in flight), and the loads of the following chunk, addressed
+// from the rewritten pointer, cannot be issued any earlier.
+template <int F>
+struct Chunk {
+    static_assert(F == 2 || F == 4 || F == 8 || F == 16 || F == 32, "chunk size");
+    static constexpr int NV = F > 16 ? F / 16 : 1;  // SGPR vectors
+    static constexpr int W = F > 16 ? 16 : F;       // floats per vector
+    typedef float vec __attribute__((ext_vector_type(W), aligned(4)));
+    vec a[NV];
+    template <int I>
+    __device__ __forceinline__ float get() const {
+        return a[I / W][I % W];
+    }
+};
+
+template <int F>
+struct TableStream {
+    uint64_t base;  // table address, rewritten (unchanged) by every next()
+    Chunk<F> cur;   // the chunk requested last
+    __device__ __forceinline__ void load(int64_t off) {  // off: floats from the table start
+        typedef const __attribute__((address_space(4))) typename Chunk<F>::vec* P;
+        const P p = reinterpret_cast<P>(base + static_cast<uint64_t>(off) * sizeof(float));
+        StaticFor<0, Chunk<F>::NV>::run([&](auto k) { cur.a[decltype(k)::value] = p[decltype(k)::value]; });
+    }
+    __device__ __forceinline__ void begin(ctab_f table, int64_t off) {
+        base = reinterpret_cast<uint64_t>(table);
+        load(off);
+    }
+    // Returns the chunk requested by the previous call and requests the one at
+    // `off` (any chunk inside the table; the last call may repeat one).
+    __device__ __forceinline__ Chunk<F> next(int64_t off) {
+        if constexpr (Chunk<F>::NV == 1)
+            asm volatile("" : "+s"(base) : "s"(cur.a[0]));
+        else
+            asm volatile("" : "+s"(base) : "s"(cur.a[0]), "s"(cur.a[1]));
+        const Chunk<F> got = cur;
+        load(off);
+        return got;
+    }
+};
 
 }  // namespace tile
 }  // namespace hygt
