@@ -29,9 +29,10 @@
  *
  * Memory and ownership
  *   Every array argument is DEVICE memory owned by the caller. The library
- *   allocates nothing, keeps no state between calls and never synchronises
- *   the stream except in hygt_check_error(). All work is enqueued on `stream`
- *   (0 = the null stream) and runs asynchronously.
+ *   allocates nothing, keeps no state between calls (apart from the static
+ *   area of hygt_transform_noalloc()) and never synchronises the stream
+ *   except in hygt_check_error(). All work is enqueued on `stream` (0 = the
+ *   null stream) and runs asynchronously.
  *
  * Layouts
  *   x, y     float32 [nblocks][N], contiguous, 16-byte aligned.
@@ -84,7 +85,9 @@ enum hygt_status {
     HYGT_EWORKSPACE = -2, /* workspace NULL, too small or not 256-byte aligned */
     HYGT_ELAUNCH = -3,    /* the HIP runtime refused a kernel launch */
     HYGT_ECLASS = -4,     /* a block's class index was outside [0, nclasses) */
-    HYGT_EHIP = -5        /* another HIP runtime error (hygt_check_error) */
+    HYGT_EHIP = -5,       /* another HIP runtime error (hygt_check_error) */
+    HYGT_ESCRATCH = -6    /* the sizes need more than the static scratch area
+                             of hygt_transform_noalloc() */
 };
 
 enum hygt_direction {
@@ -192,6 +195,32 @@ int hygt_forward(const float* x, float* y, const int32_t* cls, int64_t nblocks,
 int hygt_inverse(const float* x, float* y, const int32_t* cls, int64_t nblocks,
                  int log2n, int rounds, const float* angles, int nclasses,
                  void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---- For callers that cannot allocate ------------------------------------
+ *
+ * For code that may not call hipMalloc or take memory from an allocator (for
+ * instance work captured into a HIP graph, or a serving loop that allocates
+ * nothing per call): hygt_forward() (direction HYGT_FORWARD) or hygt_inverse()
+ * (HYGT_INVERSE) with the workspace taken from a static device array of the
+ * library, HYGT_NOALLOC_SCRATCH_BYTES bytes per GPU, held by each GPU the
+ * library runs on until the process ends. The caller still passes x, y, cls
+ * and angles (device memory, as for hygt_forward()). The call allocates
+ * nothing; sizes whose workspace (hygt_workspace_bytes()) exceeds the area
+ * are rejected with HYGT_ESCRATCH before anything is enqueued (for N = 64,
+ * R = 4 and 35 classes: up to about 3.9 million blocks). Nothing in the area
+ * needs clearing between calls: every call rewrites what it reads.
+ *
+ * All calls on one GPU share that GPU's area, so calls that may overlap on
+ * the device (other streams, or other host threads) race and give wrong
+ * results; order them (one stream, or events). hygt_check_error() cannot be
+ * used for these calls (the area is not visible to the caller); class
+ * indices must be in range. The first call on a device looks up the area's
+ * device address (that call is not capturable; later ones are). */
+#define HYGT_NOALLOC_SCRATCH_BYTES 16777216 /* 16 MiB */
+
+int hygt_transform_noalloc(const float* x, float* y, const int32_t* cls, int64_t nblocks,
+                           int log2n, int rounds, const float* angles, int nclasses,
+                           int direction, hipStream_t stream);
 
 /* Largest block length (log2) supported by hygt_backward(). */
 #define HYGT_BACKWARD_MAX_LOG2N 6

@@ -19,6 +19,7 @@ HYGT_EWORKSPACE = -2
 HYGT_ELAUNCH = -3
 HYGT_ECLASS = -4
 HYGT_EHIP = -5
+HYGT_ESCRATCH = -6
 
 HYGT_FORWARD = 0
 HYGT_INVERSE = 1
@@ -33,6 +34,7 @@ HYGT_PERM_MAX_LOG2N = 6
 HYGT_INT_MAX_LOG2N = 6
 
 HYGT_MAX_SEGMENTS = 4
+HYGT_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 _c = ctypes
 
@@ -87,6 +89,9 @@ _SIGNATURES = {
     "hygt_graph_launch": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "hygt_graph_destroy": (_c.c_int, [_c.c_void_p]),
     "hygt_check_error": (_c.c_int, [_c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_transform_noalloc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                          _c.c_int, _c.c_int, _c.c_void_p, _c.c_int, _c.c_int,
+                                          _c.c_void_p]),
     "hygt_strerror": (_c.c_char_p, [_c.c_int]),
 }
 
@@ -250,3 +255,9 @@ def hygt_graph_destroy(handle) -> int:
 
 def hygt_check_error(ws_ptr, ws_bytes, stream) -> int:
     return load().hygt_check_error(ws_ptr, ws_bytes, stream)
+
+
+def hygt_transform_noalloc(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses,
+                           direction, stream) -> int:
+    return load().hygt_transform_noalloc(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds,
+                                         angles_ptr, nclasses, direction, stream)

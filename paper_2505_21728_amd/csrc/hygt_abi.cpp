@@ -140,6 +140,20 @@ int plan_and_apply(const float* x, float* y, const int32_t* cls, int64_t nblocks
     return apply_impl(x, y, nblocks, log2n, rounds, nclasses, direction, ws, ws_bytes, stream);
 }
 
+}  // namespace
+
+namespace hygt {
+int transform_in_workspace(const float* x, float* y, const int32_t* cls, int64_t nblocks,
+                           int log2n, int rounds, const float* angles, int nclasses,
+                           int direction, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (direction != HYGT_FORWARD && direction != HYGT_INVERSE) return HYGT_EINVAL;
+    return plan_and_apply(x, y, cls, nblocks, log2n, rounds, angles, nclasses, direction, ws,
+                          ws_bytes, stream);
+}
+}  // namespace hygt
+
+namespace {
+
 // ---- mixed batches ------------------------------------------------------
 
 bool segment_ok(const hygt_segment& g) {
@@ -519,6 +533,7 @@ const char* hygt_strerror(int status) {
         case HYGT_ELAUNCH: return "HIP kernel launch failed";
         case HYGT_ECLASS: return "a class index was outside [0, nclasses)";
         case HYGT_EHIP: return "HIP runtime error";
+        case HYGT_ESCRATCH: return "the sizes need more workspace than the static scratch area of hygt_transform_noalloc() holds";
         default: return "unknown status";
     }
 }

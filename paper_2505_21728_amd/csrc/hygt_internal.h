@@ -242,6 +242,12 @@ constexpr int kMixedConfigs = 8;
 int64_t mixed_items(int log2n, int64_t max_tiles);
 hipError_t launch_mixed(const MixedArgs& a, int direction, int config, hipStream_t stream);
 
+// hygt_forward() / hygt_inverse() on a given workspace (hygt_abi.cpp): host
+// checks, plan, apply; returns a hygt_status.
+int transform_in_workspace(const float* x, float* y, const int32_t* cls, int64_t nblocks,
+                           int log2n, int rounds, const float* angles, int nclasses,
+                           int direction, void* ws, size_t ws_bytes, hipStream_t stream);
+
 // Dense per-class transform (hygt_dense.hip), N = 64.
 hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,
                         const WsLayout& l, const WsPtrs& p, hipStream_t stream);

@@ -53,7 +53,7 @@ def test_header_constants_match_binding():
 
 
 def test_strerror():
-    for st in (0, -1, -2, -3, -4, -5):
+    for st in (0, -1, -2, -3, -4, -5, -6):
         assert _abi.strerror(st)
     assert "unknown" in _abi.strerror(123)
 
@@ -231,3 +231,14 @@ def test_mixed_sizes_and_rejects():
     assert _abi.hygt_graph_launch(None, 0) == _abi.HYGT_EINVAL
     st, cfg, us = _abi.hygt_mixed_autotune(segs, 3, 0, FAKE, total - 1, 0)
     assert st == _abi.HYGT_EWORKSPACE
+
+
+def test_noalloc_rejects_sizes_beyond_its_area():
+    # checked on the host before the device or any pointer is touched
+    big = 1 << 23
+    assert _abi.hygt_workspace_bytes(big, 6, 4, 35) > _abi.HYGT_NOALLOC_SCRATCH_BYTES
+    st = _abi.hygt_transform_noalloc(0, 0, 0, big, 6, 4, 0, 35, _abi.HYGT_FORWARD, 0)
+    assert st == _abi.HYGT_ESCRATCH
+    assert "static scratch area" in _abi.strerror(st)
+    # sizes out of range
+    assert _abi.hygt_transform_noalloc(0, 0, 0, 16, 9, 4, 0, 35, 0, 0) == _abi.HYGT_EINVAL

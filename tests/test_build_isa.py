@@ -67,12 +67,14 @@ def test_every_translation_unit_has_gfx950_code(code_objects):
 def test_no_packed_fp32_instructions(code_objects):
     objdump = _tool("llvm-objdump")
     bad = re.compile(r"\bv_pk_(add|mul|fma)_f32\b")
+    kernels = 0
     for co in code_objects:
         text = subprocess.run([objdump, "-d", str(co)], check=True, capture_output=True,
                               text=True).stdout
-        assert "s_endpgm" in text
+        kernels += text.count("s_endpgm")
         hits = bad.findall(text)
         assert not hits, f"{co.name}: {len(hits)} packed FP32 instructions"
+    assert kernels > 100  # the disassembly did see the kernels
 
 
 def test_no_kernel_uses_scratch(code_objects):
@@ -82,6 +84,6 @@ def test_no_kernel_uses_scratch(code_objects):
                                text=True).stdout
         names = re.findall(r"^\s+\.name:\s+(\S+)", notes, re.M)
         sizes = re.findall(r"^\s+\.private_segment_fixed_size:\s+(\d+)", notes, re.M)
-        assert names and len(names) == len(sizes)
+        assert len(names) == len(sizes)  # a unit may hold no kernel (device data only)
         using = [n for n, s in zip(names, sizes) if int(s) != 0]
         assert not using, f"kernels with scratch memory: {using}"
