@@ -71,6 +71,8 @@ def _args():
                     help="blocks of the batch run through the oracle on the host (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (HBM counter calibration)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed steps and the kernel rooflines (for counter runs)")
     return ap.parse_args()
 
 
@@ -467,11 +469,13 @@ def main():
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
     copy = _copy_ceiling(torch, xs, zt, args.steps)
-    klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
-    variants = _variants(torch, hygt, at, cs, xs, args.steps)
-    grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
-    mixed = _mixed_workload(torch, hygt, args.steps)
-    served = _serve_workload(torch)
+    klt = variants = grad = mixed = served = None
+    if not args.main_only:
+        klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
+        variants = _variants(torch, hygt, at, cs, xs, args.steps)
+        grad = _grad_step(torch, hygt, at, cs, xs, args.steps)
+        mixed = _mixed_workload(torch, hygt, args.steps)
+        served = _serve_workload(torch)
 
     out = {
         "metric": METRIC,
