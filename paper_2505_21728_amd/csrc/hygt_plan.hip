@@ -144,6 +144,8 @@ __device__ __forceinline__ int class_tiles(int count) {
 // before round i), and round i lists its tiles by class. tiles[c'] = T_c'.
 __device__ int interleaved_position(const int* tiles, int nclasses, int c, int i) {
     int pos = 0;
+    // unrolled, so that several LDS reads are in flight at once
+#pragma unroll 8
     for (int k = 0; k < nclasses; ++k) {
         const int t = tiles[k];
         pos += t < i ? t : i;
@@ -455,14 +457,18 @@ __device__ __forceinline__ void place_chunk(int* place_dyn, int64_t k, const int
         }
     }
     // Interleaved order: the empty lanes of each class's last tile, class c
-    // by the workgroup of chunk c mod nchunks, a lane per entry.
-    if (interleave > 0 && wave == 0) {
-        for (int c = static_cast<int>(k); c < nclasses; c += static_cast<int>(nchunks)) {
-            const int total = sh.total[c];
-            const int used = total % kTile;
+    // by the workgroup of chunk c mod nchunks, a thread per class (with few
+    // chunks, one workgroup has many classes: a wavefront taking them one
+    // after another would spend most of the launch in these lookups).
+    if (interleave > 0) {
+        const int64_t cstep = static_cast<int64_t>(blockDim.x) * nchunks;
+        for (int64_t c = k + tid * nchunks; c < nclasses; c += cstep) {
+            const int used = sh.total[c] % kTile;
             if (used == 0) continue;
-            const int64_t t = interleaved_position(sh.tiles, nclasses, c, sh.tiles[c] - 1);
-            if (t < max_tiles && lane >= used) perm[t * kTile + lane] = -1;
+            const int ci = static_cast<int>(c);
+            const int64_t t = interleaved_position(sh.tiles, nclasses, ci, sh.tiles[ci] - 1);
+            if (t >= max_tiles) continue;
+            for (int ln = used; ln < kTile; ++ln) perm[t * kTile + ln] = -1;
         }
     }
     // Class of every tile of this chunk's share of the tile list (class order
