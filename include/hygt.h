@@ -325,6 +325,85 @@ int hygt_mixed_graph_create(const hygt_segment* segs, int nseg, int direction, i
 int hygt_graph_launch(hygt_graph graph, hipStream_t stream);
 int hygt_graph_destroy(hygt_graph graph);
 
+/* ---- Request queue: single-launch batches of requests (serving) ---------
+ *
+ * For a serving loop that transforms requests as they arrive (a codec's
+ * frames, Sec. VI: blocks of one size each, with a class per block), where
+ * latency rather than bulk throughput matters. The multiplier tables of each
+ * block size are built once (hygt_table_build()) and stay on the device. The
+ * requests themselves are descriptors in a ring that the caller fills and the
+ * device reads: one launch (hygt_requests_apply()) transforms a run of
+ * consecutive ring entries, with no plan, no workspace and no class grouping.
+ * Each lane takes one block and follows its own class's table (the
+ * multipliers arrive by vector loads, not as wave-uniform scalars), so a
+ * block's arithmetic, and so its result, is bit for bit that of
+ * hygt_apply() with a plan of the same angles. Bulk batches are faster
+ * through hygt_plan() + hygt_apply(), whose class-sorted tiles read each
+ * multiplier once per 64 blocks. */
+
+/* Bytes of the table of one block size (0 for invalid sizes). */
+size_t hygt_table_bytes(int log2n, int rounds, int nclasses);
+
+/* Builds the multiplier tables of both directions (the same FP64 conversion
+ * and sign bookkeeping as hygt_plan()) into `table`: device memory of at
+ * least hygt_table_bytes() bytes, 256-byte aligned, owned by the caller and
+ * read by every hygt_requests_apply() that names it. angles: device memory,
+ * [nclasses][rounds][log2n][N/2] float32, read only; 2 <= log2n <= 8. One
+ * launch of 2 * nclasses workgroups on `stream`. */
+int hygt_table_build(const float* angles, int log2n, int rounds, int nclasses, void* table,
+                     size_t table_bytes, hipStream_t stream);
+
+/* A table built by hygt_table_build(), with its sizes. */
+typedef struct hygt_table_ref {
+    const void* table;
+    int32_t log2n;
+    int32_t rounds;
+    int32_t nclasses;
+    int32_t reserved; /* 0 */
+} hygt_table_ref;
+
+/* One request: nblocks blocks of one size. */
+typedef struct hygt_request {
+    const float* x;      /* [nblocks][N] input, device memory, 16-byte aligned */
+    float* y;            /* [nblocks][N] output; may be x, must not overlap it otherwise */
+    const int32_t* cls;  /* [nblocks] classes; NULL when the table has one class */
+    int64_t nblocks;     /* 0 .. HYGT_MAX_REQUEST_BLOCKS */
+    int32_t table;       /* index into the `tables` of the call */
+    int32_t status;      /* written by the device: set to HYGT_ECLASS when some block's
+                            class is outside [0, nclasses); the caller clears it */
+    int64_t first_wg;    /* written by hygt_requests_apply(): the request's first
+                            workgroup in the launch */
+} hygt_request;
+
+#define HYGT_MAX_BATCH_REQUESTS 64
+#define HYGT_MAX_TABLES 4
+#define HYGT_MAX_REQUEST_BLOCKS (1LL << 26)
+
+/* Transforms requests ring[(first + i) % capacity], i = 0 .. count - 1
+ * (1 <= count <= HYGT_MAX_BATCH_REQUESTS), forward or inverse, in one launch
+ * on `stream`.
+ *   ring    capacity entries in pinned host memory that the device can read
+ *           and write (hipHostMalloc), 8-byte aligned; other memory is
+ *           rejected with HYGT_EINVAL (hipHostGetDevicePointer gives the
+ *           device's address of the ring). The host part of this call
+ *           reads each entry's sizes and writes its first_wg; the device
+ *           reads the entries' descriptors and, for a request with a class
+ *           out of range, writes its status. So the `count` entries must not
+ *           be rewritten, and their status read, before the stream has
+ *           passed the end of this call's work.
+ *   tables  ntables (1 .. HYGT_MAX_TABLES) table references, host memory,
+ *           read during the call; the tables themselves must stay until
+ *           the work ends.
+ * A block whose class is out of range is written as zeros (never left
+ * with stale contents) and sets its request's status. Requests with no
+ * blocks are skipped. Entry checks (sizes, table index, NULL or misaligned
+ * pointers, partial overlap of x and y) run on the host before anything is
+ * enqueued: a failing entry makes the call return HYGT_EINVAL with nothing
+ * launched. Different requests must not write overlapping outputs. */
+int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int count,
+                        const hygt_table_ref* tables, int ntables, int direction,
+                        hipStream_t stream);
+
 /* Waits for `stream`, then reports whether the last non-empty plan on this
  * workspace met a class index outside [0, nclasses) (HYGT_ECLASS), a HIP
  * error (HYGT_EHIP), or neither (HYGT_OK). Reads at most workspace_bytes

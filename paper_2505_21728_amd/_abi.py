@@ -35,6 +35,9 @@ HYGT_INT_MAX_LOG2N = 6
 
 HYGT_MAX_SEGMENTS = 4
 HYGT_NOALLOC_SCRATCH_BYTES = 16 << 20
+HYGT_MAX_BATCH_REQUESTS = 64
+HYGT_MAX_TABLES = 4
+HYGT_MAX_REQUEST_BLOCKS = 1 << 26
 
 _c = ctypes
 
@@ -47,6 +50,18 @@ class Segment(ctypes.Structure):
 
 
 _SEGS = _c.POINTER(Segment)
+
+
+class TableRef(ctypes.Structure):
+    """struct hygt_table_ref of include/hygt.h."""
+    _fields_ = [("table", _c.c_void_p), ("log2n", _c.c_int32), ("rounds", _c.c_int32),
+                ("nclasses", _c.c_int32), ("reserved", _c.c_int32)]
+
+
+# struct hygt_request of include/hygt.h, as a numpy record (the ring's layout).
+REQUEST_FIELDS = [("x", "<u8"), ("y", "<u8"), ("cls", "<u8"), ("nblocks", "<i8"),
+                  ("table", "<i4"), ("status", "<i4"), ("first_wg", "<i8")]
+REQUEST_BYTES = 48
 
 # Every exported symbol with its (restype, argtypes).
 _SIGNATURES = {
@@ -92,6 +107,11 @@ _SIGNATURES = {
     "hygt_transform_noalloc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
                                           _c.c_int, _c.c_int, _c.c_void_p, _c.c_int, _c.c_int,
                                           _c.c_void_p]),
+    "hygt_table_bytes": (_c.c_size_t, [_c.c_int, _c.c_int, _c.c_int]),
+    "hygt_table_build": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_int, _c.c_void_p,
+                                    _c.c_size_t, _c.c_void_p]),
+    "hygt_requests_apply": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int64, _c.c_int,
+                                       _c.POINTER(TableRef), _c.c_int, _c.c_int, _c.c_void_p]),
     "hygt_strerror": (_c.c_char_p, [_c.c_int]),
 }
 
@@ -261,3 +281,27 @@ def hygt_transform_noalloc(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles
                            direction, stream) -> int:
     return load().hygt_transform_noalloc(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds,
                                          angles_ptr, nclasses, direction, stream)
+
+
+def hygt_table_bytes(log2n, rounds, nclasses) -> int:
+    return int(load().hygt_table_bytes(log2n, rounds, nclasses))
+
+
+def hygt_table_build(angles_ptr, log2n, rounds, nclasses, table_ptr, table_bytes, stream) -> int:
+    return load().hygt_table_build(angles_ptr, log2n, rounds, nclasses, table_ptr, table_bytes,
+                                   stream)
+
+
+def table_refs(items) -> "ctypes.Array[TableRef]":
+    """A ctypes array of hygt_table_ref from (table, log2n, rounds, nclasses)
+    tuples (pointers as ints)."""
+    arr = (TableRef * len(items))()
+    for i, (t, d, r, c) in enumerate(items):
+        arr[i] = TableRef(t, d, r, c, 0)
+    return arr
+
+
+def hygt_requests_apply(ring_ptr, capacity, first, count, tables, ntables, direction,
+                        stream) -> int:
+    return load().hygt_requests_apply(ring_ptr, capacity, first, count, tables, ntables,
+                                      direction, stream)

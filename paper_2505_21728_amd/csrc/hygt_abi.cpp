@@ -12,6 +12,10 @@
 #include "hygt_internal.h"
 
 static_assert(HYGT_MAX_SEGMENTS == hygt::kMaxSegments, "segment limits differ");
+static_assert(HYGT_MAX_TABLES == hygt::kMaxReqTables, "table limits differ");
+static_assert(HYGT_MAX_BATCH_REQUESTS == hygt::kMaxBatchRequests && HYGT_MAX_BATCH_REQUESTS <= 64,
+              "a batch's descriptors are read a lane each");
+static_assert(sizeof(hygt_request) == 48 && sizeof(hygt_table_ref) == 24, "descriptor layout");
 
 namespace {
 
@@ -503,6 +507,83 @@ int hygt_graph_destroy(hygt_graph graph) {
     if (hipGraphDestroy(graph->graph) != hipSuccess) status = HYGT_EHIP;
     delete graph;
     return status;
+}
+
+size_t hygt_table_bytes(int log2n, int rounds, int nclasses) {
+    if (log2n < 2 || log2n > HYGT_MAX_LOG2N || rounds < 1 || rounds > HYGT_MAX_ROUNDS ||
+        nclasses < 1 || nclasses > HYGT_MAX_CLASSES)
+        return 0;
+    return hygt::table_layout(log2n, rounds, nclasses).total;
+}
+
+int hygt_table_build(const float* angles, int log2n, int rounds, int nclasses, void* table,
+                     size_t table_bytes, hipStream_t stream) {
+    const size_t need = hygt_table_bytes(log2n, rounds, nclasses);
+    if (need == 0 || angles == nullptr || !aligned(angles, 4)) return HYGT_EINVAL;
+    if (table == nullptr || table_bytes < need || !aligned(table, 256)) return HYGT_EWORKSPACE;
+    const hipError_t e = hygt::launch_table_build(angles, log2n, rounds, nclasses,
+                                                  hygt::table_layout(log2n, rounds, nclasses),
+                                                  table, stream);
+    return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
+}
+
+int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int count,
+                        const hygt_table_ref* tables, int ntables, int direction,
+                        hipStream_t stream) {
+    if (direction != HYGT_FORWARD && direction != HYGT_INVERSE) return HYGT_EINVAL;
+    if (ring == nullptr || !aligned(ring, 8) || capacity < 1 || first < 0 || count < 1 ||
+        count > HYGT_MAX_BATCH_REQUESTS || count > capacity)
+        return HYGT_EINVAL;
+    if (tables == nullptr || ntables < 1 || ntables > HYGT_MAX_TABLES) return HYGT_EINVAL;
+    hygt::RequestArgs a{};
+    for (int i = 0; i < ntables; ++i) {
+        const hygt_table_ref& t = tables[i];
+        if (hygt_table_bytes(t.log2n, t.rounds, t.nclasses) == 0 || t.table == nullptr ||
+            !aligned(t.table, 256))
+            return HYGT_EINVAL;
+        const hygt::TableLayout l = hygt::table_layout(t.log2n, t.rounds, t.nclasses);
+        const char* b = static_cast<const char*>(t.table);
+        a.tab[i].modes = reinterpret_cast<const int32_t*>(b + l.modes);
+        a.tab[i].coef = reinterpret_cast<const float*>(b + l.coef);
+        a.tab[i].signs = reinterpret_cast<const float*>(b + l.signs);
+        a.tab[i].log2n = t.log2n;
+        a.tab[i].rounds = t.rounds;
+        a.tab[i].nclasses = t.nclasses;
+    }
+    first %= capacity;
+    // every entry is checked before any is written or anything launched
+    for (int i = 0; i < count; ++i) {
+        const hygt_request& e = ring[(first + i) % capacity];
+        if (e.table < 0 || e.table >= ntables) return HYGT_EINVAL;
+        if (e.nblocks < 0 || e.nblocks > HYGT_MAX_REQUEST_BLOCKS) return HYGT_EINVAL;
+        if (e.nblocks == 0) continue;
+        const hygt_table_ref& t = tables[e.table];
+        if (e.x == nullptr || e.y == nullptr || !aligned(e.x, 16) || !aligned(e.y, 16))
+            return HYGT_EINVAL;
+        if (!overlap_ok(e.x, e.y, e.nblocks, t.log2n)) return HYGT_EINVAL;
+        if (e.cls == nullptr ? t.nclasses != 1 : !aligned(e.cls, 4)) return HYGT_EINVAL;
+    }
+    int64_t wgs = 0;
+    for (int i = 0; i < count; ++i) {
+        hygt_request& e = ring[(first + i) % capacity];
+        e.first_wg = wgs;
+        wgs += hygt::request_workgroups(e.nblocks, tables[e.table].log2n);
+    }
+    if (wgs == 0) return HYGT_OK;
+    // The device's address of the ring; fails (and nothing is launched) for
+    // memory that is not pinned, device-accessible host memory.
+    void* dring = nullptr;
+    if (hipHostGetDevicePointer(&dring, ring, 0) != hipSuccess || dring == nullptr) {
+        (void)hipGetLastError();  // clear the error this leaves behind
+        return HYGT_EINVAL;
+    }
+    a.ring = dring;
+    a.capacity = capacity;
+    a.first = first;
+    a.count = count;
+    a.ntables = ntables;
+    const hipError_t err = hygt::launch_requests(a, wgs, direction, stream);
+    return err == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 
 int hygt_check_error(const void* workspace, size_t workspace_bytes, hipStream_t stream) {

@@ -248,6 +248,70 @@ int transform_in_workspace(const float* x, float* y, const int32_t* cls, int64_t
                            int log2n, int rounds, const float* angles, int nclasses,
                            int direction, void* ws, size_t ws_bytes, hipStream_t stream);
 
+// A stand-alone multiplier table of one block size (hygt_table_build()):
+// the modes, coef and signs parts of a workspace, for both directions.
+struct TableLayout {
+    size_t modes = 0;  // int32 [2][C]
+    size_t coef = 0;   // float [2][C][P][N]
+    size_t signs = 0;  // float [2][C][N]
+    size_t total = 0;
+    int passes = 0;
+    int n = 0;
+};
+
+inline TableLayout table_layout(int log2n, int rounds, int nclasses) {
+    TableLayout t;
+    t.n = 1 << log2n;
+    t.passes = rounds * log2n;
+    const size_t C = static_cast<size_t>(nclasses);
+    t.modes = 0;
+    t.coef = align_up(2 * C * 4, 256);
+    t.signs = align_up(t.coef + 2 * C * static_cast<size_t>(t.passes) * t.n * 4, 256);
+    t.total = align_up(t.signs + 2 * C * static_cast<size_t>(t.n) * 4, 256);
+    return t;
+}
+
+// Builds the tables of both directions into `table` (hygt_plan.hip).
+hipError_t launch_table_build(const float* angles, int log2n, int rounds, int nclasses,
+                              const TableLayout& t, void* table, hipStream_t stream);
+
+// One table of a request launch, with its parts resolved.
+struct ReqTable {
+    const int32_t* modes;
+    const float* coef;
+    const float* signs;
+    int log2n;
+    int rounds;
+    int nclasses;
+    int pad;
+};
+
+// Arguments of a request launch (hygt_request.hip). `ring` points to
+// hygt_request entries (include/hygt.h), seen here as raw memory so that
+// this header needs no part of the public one.
+constexpr int kMaxReqTables = 4;
+constexpr int kMaxBatchRequests = 64;
+struct RequestArgs {
+    void* ring;
+    int64_t capacity;
+    int64_t first;
+    int count;
+    int ntables;
+    ReqTable tab[kMaxReqTables];
+};
+
+// Workgroups (of four wavefronts) of a request of nblocks blocks of 2^log2n
+// values: four tiles of 64 blocks per workgroup for N <= 64, two for
+// N = 128, one for N = 256.
+inline int64_t request_workgroups(int64_t nblocks, int log2n) {
+    const int64_t tiles = (nblocks + kTile - 1) / kTile;
+    const int64_t per = log2n > kLaneBits ? 4 >> (log2n - kLaneBits) : 4;
+    return (tiles + per - 1) / per;
+}
+
+hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, int direction,
+                           hipStream_t stream);
+
 // Dense per-class transform (hygt_dense.hip), N = 64.
 hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,
                         const WsLayout& l, const WsPtrs& p, hipStream_t stream);

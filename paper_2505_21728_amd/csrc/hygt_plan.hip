@@ -242,6 +242,20 @@ __device__ __forceinline__ void build_tables_wg(int* place_dyn, int w, const flo
                 modes + t, nullptr);
 }
 
+// Stand-alone tables (hygt_table_build()): workgroup w builds (direction,
+// class) = (w / C, w % C), laid out as in a workspace.
+__global__ __launch_bounds__(kPlanThreads) void table_build_kernel(
+    const float* __restrict__ angles, int log2n, int rounds, int nclasses,
+    int32_t* __restrict__ modes, float* __restrict__ coef, float* __restrict__ signs) {
+    __shared__ TableShared sh;
+    const int w = blockIdx.x;
+    const size_t passes = static_cast<size_t>(rounds) * log2n;
+    const size_t n = size_t{1} << log2n;
+    build_table(sh, w / nclasses, w % nclasses, angles, nullptr, log2n, rounds,
+                coef + static_cast<size_t>(w) * passes * n, signs + static_cast<size_t>(w) * n,
+                modes + w, nullptr);
+}
+
 // Blocks of class c in chunk k.
 __device__ __forceinline__ int chunk_class_count(const PlaceLds& sh, const int32_t* __restrict__ counts,
                                                  bool cached, int64_t k, int nclasses, int c) {
@@ -577,6 +591,16 @@ hipError_t launch_plan(const int32_t* cls, int64_t nblocks, int log2n, int round
                        dim3(kPlanThreads), lds, stream, cls, nblocks, nclasses, l.nchunks, l.chunk,
                        l.max_tiles, l.interleave, p.counts, p.tile_class, p.perm, angles, codes, log2n,
                        rounds, integer, p.modes, p.coef, p.signs);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_build(const float* angles, int log2n, int rounds, int nclasses,
+                              const TableLayout& t, void* table, hipStream_t stream) {
+    char* b = static_cast<char*>(table);
+    hipLaunchKernelGGL(table_build_kernel, dim3(static_cast<unsigned>(2 * nclasses)),
+                       dim3(kPlanThreads), 0, stream, angles, log2n, rounds, nclasses,
+                       reinterpret_cast<int32_t*>(b + t.modes), reinterpret_cast<float*>(b + t.coef),
+                       reinterpret_cast<float*>(b + t.signs));
     return hipGetLastError();
 }
 

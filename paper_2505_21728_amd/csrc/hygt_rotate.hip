@@ -63,7 +63,9 @@
 // same rounding whatever the batch, tile or launch.
 
 #include <algorithm>
+#include <climits>
 
+#include "hygt.h"
 #include "hygt_tile.h"
 
 namespace hygt {
@@ -190,20 +192,20 @@ __device__ __forceinline__ void apply_signs(float (&v)[V], ctab_f sign, int has_
 // two swap their values through LDS, 16 per lane at a time, and each
 // computes its own outputs: y_m = c x_m + s x_n on the lower wavefront,
 // y_n = c x_n - s x_m on the upper one, with (c, s) of pair i the two floats
-// at 2i of the wavefront pair's part of the pass (128 floats from `off`, in
-// four chunks of 16 pairs). `xo` is this wavefront's exchange area and `xp`
-// the partner's, each two buffers of [4][64] float4; part g uses buffer
-// g % 2, so the barrier of part g + 1 also guarantees that both wavefronts
-// have read part g before either overwrites its buffer. Every wavefront of
-// the workgroup passes the same barriers. `after` is the table offset of the
-// chunk that follows the pass.
-__device__ __forceinline__ void cross_pass(float (&v)[64], TableStream<32>& ts, int64_t off,
-                                           int64_t after, unsigned hbit, float4* xo,
-                                           const float4* xp, int lane) {
+// at 2i of the wavefront pair's part of the pass (128 floats, four chunks of
+// 16 pairs, part g's chunk returned by next_chunk(g) for the compile-time
+// g). `xo` is this wavefront's exchange area and `xp` the partner's, each
+// two buffers of [4][64] float4; part g uses buffer g % 2, so the barrier of
+// part g + 1 also guarantees that both wavefronts have read part g before
+// either overwrites its buffer. Every wavefront of the workgroup passes the
+// same barriers.
+template <class NextChunk>
+__device__ __forceinline__ void cross_pass(float (&v)[64], NextChunk&& next_chunk, unsigned hbit,
+                                           float4* xo, const float4* xp, int lane) {
     StaticFor<0, 4>::run([&](auto gg) {
         constexpr int g = decltype(gg)::value;
         constexpr int buf = g & 1;
-        const Chunk<32> m = ts.next(g + 1 < 4 ? off + 32 * (g + 1) : after);
+        const Chunk<32> m = next_chunk(gg);
         StaticFor<0, 4>::run([&](auto qq) {
             constexpr int q = decltype(qq)::value;
             constexpr int e = 16 * g + 4 * q;
@@ -224,7 +226,7 @@ __device__ __forceinline__ void cross_pass(float (&v)[64], TableStream<32>& ts, 
             constexpr int j = 16 * g + t;
             const float c = m.template get<2 * t>();
             const float sn = m.template get<2 * t + 1>();
-            // -s on the upper wavefront: a sign-bit flip of a wave-uniform value
+            // -s on the upper wavefront: a sign-bit flip
             const float sg = __uint_as_float(__float_as_uint(sn) ^ hbit);
             v[j] = fmaf(sg, w[t], c * v[j]);
         });
@@ -239,23 +241,29 @@ __device__ __forceinline__ void cross_pass(float (&v)[64], TableStream<32>& ts, 
 // start at 64 * (q without bit K-6). Then the final signs of elements
 // 64q .. 64q + 63. The tile's wavefronts have consecutive LDS areas of 512
 // float4 starting at `area0`.
+//
+// Table offset of the first chunk of wavefront q's share of pass kk
+// (application order) of round r.
+template <int D, int DIR>
+__device__ __forceinline__ int64_t split_first(int64_t r, int kk, int q) {
+    constexpr int N = 1 << D;
+    constexpr int V = 64;
+    const int K = DIR == 0 ? kk : D - 1 - kk;
+    const int64_t off = (r * D + kk) * N;
+    if (K >= kLaneBits) {
+        const int b = K - kLaneBits;
+        const int qq = ((q >> (b + 1)) << b) | (q & ((1 << b) - 1));
+        return off + 2 * V * qq;
+    }
+    return off + q * V;
+}
+
 template <int D, int DIR>
 __device__ __forceinline__ void run_passes_split(float (&v)[64], ctab_f tbl, ctab_f sign,
                                                  int has_neg, int rounds, int q, float4* area0,
                                                  int lane) {
-    constexpr int N = 1 << D;
     constexpr int V = 64;
-    // table offset of the first chunk of pass kk (application order) of round r
-    auto first = [&](int64_t r, int kk) -> int64_t {
-        const int K = DIR == 0 ? kk : D - 1 - kk;
-        int64_t off = (r * D + kk) * N;
-        if (K >= kLaneBits) {
-            const int b = K - kLaneBits;
-            const int qq = ((q >> (b + 1)) << b) | (q & ((1 << b) - 1));
-            return off + 2 * V * qq;
-        }
-        return off + q * V;
-    };
+    auto first = [&](int64_t r, int kk) -> int64_t { return split_first<D, DIR>(r, kk, q); };
     TableStream<32> ts;
     ts.begin(tbl, first(0, 0));
     for (int r = 0; r < rounds; ++r) {
@@ -267,8 +275,14 @@ __device__ __forceinline__ void run_passes_split(float (&v)[64], ctab_f tbl, cta
             const int64_t after = k + 1 < D ? first(r, k + 1) : first(rnext, 0);
             if constexpr (K >= kLaneBits) {
                 constexpr int b = K - kLaneBits;
-                cross_pass(v, ts, off, after, static_cast<unsigned>((q >> b) & 1) << 31,
-                           area0 + 512 * q, area0 + 512 * (q ^ (1 << b)), lane);
+                cross_pass(
+                    v,
+                    [&](auto gg) {
+                        constexpr int g = decltype(gg)::value;
+                        return ts.next(g + 1 < 4 ? off + 32 * (g + 1) : after);
+                    },
+                    static_cast<unsigned>((q >> b) & 1) << 31, area0 + 512 * q,
+                    area0 + 512 * (q ^ (1 << b)), lane);
             } else {
                 const Chunk<32> m0 = ts.next(off + 32);
                 lift_chunk<kLaneBits, K, 0, 32>(v, m0);
@@ -784,6 +798,342 @@ hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, i
                          hipStream_t stream) {
     if (direction == 0) return launch_dir<0>(x, y, nblocks, log2n, rounds, nclasses, l, p, stream);
     return launch_dir<1>(x, y, nblocks, log2n, rounds, nclasses, l, p, stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// Request batches: one launch over a run of request descriptors, with a lane
+// per block that follows its own class's table
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// A lane's own multiplier table, read with 16-byte vector loads two chunks
+// ahead of their use. The lanes of a wavefront hold blocks of different
+// classes here, so the multipliers cannot be wave-uniform scalars. next()
+// passes the older chunk to an empty asm statement that also rewrites the
+// table address: the compiler waits for that chunk there (while the younger
+// one stays in flight), and the load issued next, addressed from the
+// rewritten value, cannot move above it.
+template <int F>
+struct LaneStream {
+    static_assert(F >= 4, "chunks of whole 16-byte loads");
+    uint64_t base;
+    Chunk<F> c0, c1;  // requested, oldest first
+    __device__ __forceinline__ void load(Chunk<F>& c, int64_t off) {
+        constexpr int W = Chunk<F>::W;
+        // global (not generic) loads: they count only against vmcnt
+        typedef float vf4 __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(1))) vf4* gptr;
+        const gptr p = reinterpret_cast<gptr>(base + static_cast<uint64_t>(off) * 4);
+        StaticFor<0, F / 4>::run([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            const vf4 f = p[k];
+            c.a[(4 * k) / W][(4 * k) % W] = f.x;
+            c.a[(4 * k + 1) / W][(4 * k + 1) % W] = f.y;
+            c.a[(4 * k + 2) / W][(4 * k + 2) % W] = f.z;
+            c.a[(4 * k + 3) / W][(4 * k + 3) % W] = f.w;
+        });
+    }
+    __device__ __forceinline__ void begin(const float* table, int64_t off0, int64_t off1) {
+        base = reinterpret_cast<uint64_t>(table);
+        load(c0, off0);
+        load(c1, off1);
+    }
+    // Returns the oldest requested chunk and requests the one at `off`.
+    __device__ __forceinline__ Chunk<F> next(int64_t off) {
+        if constexpr (Chunk<F>::NV == 1)
+            asm volatile("" : "+v"(base) : "v"(c0.a[0]));
+        else
+            asm volatile("" : "+v"(base) : "v"(c0.a[0]), "v"(c0.a[1]));
+        const Chunk<F> got = c0;
+        c0 = c1;
+        load(c1, off);
+        return got;
+    }
+};
+
+// R rounds of D passes (N <= 64) with a lane's own table, which holds the
+// chunks in application order one after another.
+template <int D, int DIR>
+__device__ __forceinline__ void lane_rounds(float (&v)[1 << D], const float* tbl, int rounds) {
+    constexpr int N = 1 << D;
+    constexpr int F = chunk_floats<D>();
+    constexpr int CPP = N / F;
+    constexpr int CPR = D * CPP;
+    const int64_t last = static_cast<int64_t>(rounds) * CPR - 1;  // index of the last chunk
+    LaneStream<F> ls;
+    ls.begin(tbl, 0, last >= 1 ? F : 0);
+    for (int r = 0; r < rounds; ++r) {
+        StaticFor<0, CPR>::run([&](auto ee) {
+            constexpr int e = decltype(ee)::value;
+            constexpr int kk = e / CPP;
+            constexpr int H = e % CPP;
+            constexpr int K = DIR == 0 ? kk : D - 1 - kk;
+            const int64_t ahead = static_cast<int64_t>(r) * CPR + e + 2;
+            const Chunk<F> m = ls.next((ahead <= last ? ahead : last) * F);
+            lift_chunk<D, K, H, F>(v, m);
+        });
+    }
+}
+
+// Chunks of 16 pairs in one round of a split tile (N >= 128), in the order
+// they are used: two per pass along bits 0..5, four per pass along bits 6, 7.
+template <int D, int DIR>
+constexpr int split_pass_chunks(int kk) {
+    return (DIR == 0 ? kk : D - 1 - kk) >= kLaneBits ? 4 : 2;
+}
+template <int D, int DIR>
+constexpr int split_chunks_before(int kk) {
+    int n = 0;
+    for (int i = 0; i < kk; ++i) n += split_pass_chunks<D, DIR>(i);
+    return n;
+}
+template <int D, int DIR>
+constexpr int split_chunk_pass(int j) {
+    int kk = 0;
+    while (j >= split_pass_chunks<D, DIR>(kk)) {
+        j -= split_pass_chunks<D, DIR>(kk);
+        ++kk;
+    }
+    return kk;
+}
+
+// As run_passes_split, with a lane's own table.
+template <int D, int DIR>
+__device__ __forceinline__ void lane_passes_split(float (&v)[64], const float* tbl, int rounds,
+                                                  int q, float4* area0, int lane) {
+    constexpr int CR = split_chunks_before<D, DIR>(D);
+    // table offset of chunk J of round r
+    auto off_of = [&](int64_t r, auto jj) -> int64_t {
+        constexpr int J = decltype(jj)::value;
+        constexpr int kk = split_chunk_pass<D, DIR>(J);
+        return split_first<D, DIR>(r, kk, q) + 32 * (J - split_chunks_before<D, DIR>(kk));
+    };
+    // the chunk two after chunk J of round r (past the last: the last again)
+    auto ahead = [&](int64_t r, auto jj) -> int64_t {
+        constexpr int J = decltype(jj)::value + 2;
+        if constexpr (J < CR) {
+            return off_of(r, std::integral_constant<int, J>{});
+        } else {
+            if (r + 1 < rounds) return off_of(r + 1, std::integral_constant<int, J - CR>{});
+            return off_of(r, std::integral_constant<int, CR - 1>{});
+        }
+    };
+    LaneStream<32> ls;
+    ls.begin(tbl, off_of(0, std::integral_constant<int, 0>{}),
+             off_of(0, std::integral_constant<int, 1>{}));
+    for (int r = 0; r < rounds; ++r) {
+        StaticFor<0, D>::run([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            constexpr int K = DIR == 0 ? k : D - 1 - k;
+            constexpr int j0 = split_chunks_before<D, DIR>(k);
+            if constexpr (K >= kLaneBits) {
+                constexpr int b = K - kLaneBits;
+                cross_pass(
+                    v,
+                    [&](auto gg) {
+                        constexpr int g = decltype(gg)::value;
+                        return ls.next(ahead(r, std::integral_constant<int, j0 + g>{}));
+                    },
+                    static_cast<unsigned>((q >> b) & 1) << 31, area0 + 512 * q,
+                    area0 + 512 * (q ^ (1 << b)), lane);
+            } else {
+                const Chunk<32> m0 = ls.next(ahead(r, std::integral_constant<int, j0>{}));
+                lift_chunk<kLaneBits, K, 0, 32>(v, m0);
+                const Chunk<32> m1 = ls.next(ahead(r, std::integral_constant<int, j0 + 1>{}));
+                lift_chunk<kLaneBits, K, 1, 32>(v, m1);
+            }
+        });
+    }
+}
+
+// Local workgroup lw of a request of N = 2^D blocks: tiles of 64 consecutive
+// blocks, four per workgroup (a wavefront each) for N <= 64, two for N = 128
+// and one for N = 256 (2^(D-6) wavefronts each, wavefront q holding values
+// 64q .. 64q+63 of every block). A lane loads its block's class; one outside
+// [0, nclasses) sets the request's status, runs with class 0's table and
+// writes zeros. The tiles of a workgroup of N >= 128 pass the same
+// barriers, a tile past the request's end included (it touches no block).
+template <int D, int DIR>
+__device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __restrict__ x,
+                                             float* __restrict__ y,
+                                             const int32_t* __restrict__ cls, int64_t nblocks,
+                                             int64_t lw, int wv, int lane, float4 (*lds)[512],
+                                             int32_t* status) {
+    using G = TileGeo<D>;
+    constexpr int N = G::N;
+    constexpr int S = G::SHARE;
+    constexpr int V = G::V;
+    constexpr int CHP = G::CHP;
+    const int q = wv % S;
+    const int64_t t = lw * (4 / S) + wv / S;
+    const int64_t ntiles = (nblocks + kTile - 1) / kTile;
+    if (!G::SPLIT && t >= ntiles) return;
+    const int64_t b64 = t * kTile + lane;
+    const int blk = (t < ntiles && b64 < nblocks) ? static_cast<int>(b64) : -1;
+    int c = 0;
+    if (blk >= 0 && cls != nullptr) c = cls[blk];
+    const bool bad = blk >= 0 && (c < 0 || c >= tb.nclasses);
+    if (bad) {
+        __hip_atomic_store(status, static_cast<int32_t>(HYGT_ECLASS), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        c = 0;
+    }
+    const size_t table = static_cast<size_t>(DIR) * tb.nclasses + c;
+    const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * D * N;
+    float v[V];
+    if constexpr (G::SPLIT) {
+        load_row<D>(x + q * V, blk, v);
+        lane_passes_split<D, DIR>(v, tbl, tb.rounds, q, lds[wv - q], lane);
+        // the partners' last reads of this wavefront's area come before the
+        // staging of the stores below
+        __syncthreads();
+    } else {
+        // t < ntiles: block 0 of the request exists for lanes without a block
+        load_tile<D>(x, blk, v, lds[wv], lane);
+        lane_rounds<D, DIR>(v, tbl, tb.rounds);
+    }
+    if (tb.modes[table]) {
+        const float* sg = tb.signs + table * N + q * V;
+        StaticFor<0, V>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            v[i] *= sg[i];
+        });
+    }
+    if (bad) {
+        StaticFor<0, V>::run([&](auto ii) { v[decltype(ii)::value] = 0.0f; });
+    }
+    int lane2 = lane;
+    asm volatile("" : "+v"(lane2));
+    const int sw2 = swz<CHP>(lane2);
+    int b = blk;
+    asm volatile("" : "+v"(b));
+    int bb[CHP];
+    instr_blocks<D>(bb, b, lane2);
+    StaticFor<0, G::PARTS>::run([&](auto pp) {
+        store_part<D, decltype(pp)::value>(y + q * V, lds[wv], bb, v, lane2, sw2);
+    });
+}
+
+// The address u, of global memory, as a pointer that the compiler knows to
+// be global (made from the integer as a global pointer, then converted), so
+// that every access derived from it is a global rather than a generic
+// (flat) load or store.
+// The ring lives in host memory, written by the host between launches:
+// its fields are read, and the status written, at system scope, so that no
+// cache between the device and host memory can hold a stale copy whatever
+// the coherence of the host allocation.
+template <typename T>
+__device__ __forceinline__ T ring_load(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename T>
+__device__ __forceinline__ T* global_ptr(uint64_t u) {
+    typedef __attribute__((address_space(1))) T* G;
+    return (T*)reinterpret_cast<G>(u);
+}
+
+__device__ __forceinline__ uint64_t read_lane64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(v), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), l);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Table ti of the launch, field by field as masked ORs of the wave-uniform
+// arguments: selects would be folded back into an access of the argument
+// array at a run-time index, which the compiler serves from a copy of the
+// arguments in scratch memory.
+__device__ __forceinline__ ReqTable pick_table(const RequestArgs& a, int ti) {
+    uint64_t modes = 0, coef = 0, signs = 0;
+    int log2n = 0, rounds = 0, nclasses = 0;
+    StaticFor<0, kMaxReqTables>::run([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const uint64_t m = 0 - static_cast<uint64_t>(ti == k);
+        const int mi = static_cast<int>(m);
+        modes |= reinterpret_cast<uint64_t>(a.tab[k].modes) & m;
+        coef |= reinterpret_cast<uint64_t>(a.tab[k].coef) & m;
+        signs |= reinterpret_cast<uint64_t>(a.tab[k].signs) & m;
+        log2n |= a.tab[k].log2n & mi;
+        rounds |= a.tab[k].rounds & mi;
+        nclasses |= a.tab[k].nclasses & mi;
+    });
+    ReqTable t;
+    t.modes = reinterpret_cast<const int32_t*>(modes);
+    t.coef = reinterpret_cast<const float*>(coef);
+    t.signs = reinterpret_cast<const float*>(signs);
+    t.log2n = log2n;
+    t.rounds = rounds;
+    t.nclasses = nclasses;
+    t.pad = 0;
+    return t;
+}
+
+// Workgroup w belongs to the last of the batch's requests whose first
+// workgroup is <= w (first_wg is non-decreasing along the batch, and a
+// request without blocks shares its first workgroup with the next one).
+// Lane i of every wavefront reads entry i's descriptor, so the batch costs
+// one round trip to the ring; the chosen request's fields are then read
+// from its lane.
+template <int DIR>
+__global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
+    __shared__ float4 lds[4][512];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = blockIdx.x;
+    hygt_request* ring = static_cast<hygt_request*>(a.ring);
+    int64_t idx = 0, fw = INT64_MAX, nb = 0;
+    uint64_t ex = 0, ey = 0, ec = 0;
+    int et = 0;
+    if (lane < a.count) {
+        idx = a.first + lane;  // first < capacity and count <= capacity
+        if (idx >= a.capacity) idx -= a.capacity;
+        hygt_request* e = ring + idx;
+        fw = ring_load(&e->first_wg);
+        nb = ring_load(&e->nblocks);
+        ex = reinterpret_cast<uint64_t>(ring_load(&e->x));
+        ey = reinterpret_cast<uint64_t>(ring_load(&e->y));
+        ec = reinterpret_cast<uint64_t>(ring_load(&e->cls));
+        et = ring_load(&e->table);
+    }
+    const uint64_t below = __ballot(lane < a.count && fw <= w);
+    const int r = __builtin_amdgcn_readfirstlane(__popcll(below) - 1);
+    if (r < 0) return;  // not reached: the first entry's first workgroup is 0
+    const int64_t first_wg = static_cast<int64_t>(read_lane64(static_cast<uint64_t>(fw), r));
+    const int64_t nblocks = static_cast<int64_t>(read_lane64(static_cast<uint64_t>(nb), r));
+    const float* x = global_ptr<const float>(read_lane64(ex, r));
+    float* y = global_ptr<float>(read_lane64(ey, r));
+    const int32_t* cls = global_ptr<const int32_t>(read_lane64(ec, r));
+    int32_t* status = &ring[read_lane64(static_cast<uint64_t>(idx), r)].status;
+    ReqTable tb = pick_table(a, __builtin_amdgcn_readlane(et, r));
+    tb.modes = global_ptr<const int32_t>(reinterpret_cast<uint64_t>(tb.modes));
+    tb.coef = global_ptr<const float>(reinterpret_cast<uint64_t>(tb.coef));
+    tb.signs = global_ptr<const float>(reinterpret_cast<uint64_t>(tb.signs));
+    const int64_t lw = w - first_wg;
+    switch (tb.log2n) {
+        case 2: request_tile<2, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 3: request_tile<3, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 4: request_tile<4, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 5: request_tile<5, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 6: request_tile<6, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 7: request_tile<7, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 8: request_tile<8, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        default: break;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, int direction,
+                           hipStream_t stream) {
+    if (workgroups <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>(workgroups));
+    if (direction == 0)
+        hipLaunchKernelGGL((request_kernel<0>), grid, dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((request_kernel<1>), grid, dim3(256), 0, stream, a);
+    return hipGetLastError();
 }
 
 }  // namespace hygt

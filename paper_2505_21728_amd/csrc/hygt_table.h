@@ -88,11 +88,12 @@ __device__ __forceinline__ double code_angle(uint8_t q) {
 //                   stored values' rotation sense is reversed.
 // The FP64 conversion of a batch of angles runs in parallel; only the sign
 // walk through the passes is sequential.
-__device__ inline void build_table(TableShared& sh, int dir, int c,
-                                   const float* __restrict__ angles,
-                                   const uint8_t* __restrict__ codes, int log2n, int rounds,
-                                   float* __restrict__ cbase, float* __restrict__ sbase,
-                                   int32_t* __restrict__ mode, uint32_t* __restrict__ pair_flip) {
+__device__ __forceinline__ void build_table(TableShared& sh, int dir, int c,
+                                            const float* __restrict__ angles,
+                                            const uint8_t* __restrict__ codes, int log2n,
+                                            int rounds, float* __restrict__ cbase,
+                                            float* __restrict__ sbase, int32_t* __restrict__ mode,
+                                            uint32_t* __restrict__ pair_flip) {
     const int tid = threadIdx.x;
     const int n = 1 << log2n;
     const int half = n >> 1;

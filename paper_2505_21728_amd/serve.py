@@ -1,23 +1,30 @@
 """Continuous batching of transform requests on one GPU.
 
 Requests arrive over time (a codec's frames: each a set of blocks of one
-size, with a class per block). The server keeps every size's angle table on
-the device and runs batches in a ring of slots; each slot has its own stream,
-staging buffers whose capacity caps the memory a batch may use, and
-workspace. Whenever a slot is free, the requests waiting in the queue are
-admitted first come, first served while they fit its capacity, planned, and
-transformed by one mixed launch (hygt_mixed_plan + hygt_mixed_apply).
-A batch of at most four requests (the segments one launch takes) is
-transformed in place of its requests' own tensors: each request is a
-segment, read from its input and written to its output, with no copies.
-Larger batches are gathered into the slot's per-size buffers, and each
-result is copied out into its request's output. Requests that arrive while
-batches run wait for the next free slot, so batches overlap on the device.
-Each result is stamped with the time its batch finished on the device.
+size, with a class per block). The server keeps, per block size, the
+multiplier tables built once from the angles (hygt_table_build) in device
+memory, and a ring of request descriptors in pinned host memory that the
+device reads itself: submit() writes a request's descriptor into the ring at
+once, and a batch is one launch (hygt_requests_apply) over a run of
+consecutive ring entries, reading each request's blocks from its own input
+tensor and writing its own output tensor. There is no plan, no staging copy
+and no per-batch workspace: a lane of the kernel takes one block and follows
+its own class's table.
+
+Batches run in a ring of slots, each with its own stream. Whenever a slot is
+free, the requests at the head of the queue are admitted first come, first
+served while the batch stays within the slot's capacity per block size (the
+memory cap of a batch) and the launch's request limit; requests that arrive
+while batches run wait for the next free slot, so batches overlap on the
+device. Each result is stamped with the time its batch finished on the
+device, and each request gets the status that the device wrote into its ring
+entry (HYGT_ECLASS when a class index was out of range: such blocks come out
+as zeros, never with another request's data).
 
 Every block's result depends only on the block, its class and the angles,
-so a request's output is bit-identical whether it is served alone or in any
-mix (tests/test_gpu_serve.py checks this).
+and the request kernel does a block's arithmetic exactly as the class-sorted
+kernels do, so a request's output is bit-identical whether it is served
+alone, in any mix, or through hygt_plan + hygt_apply.
 """
 
 from __future__ import annotations
@@ -26,7 +33,7 @@ import collections
 import time
 from dataclasses import dataclass, field
 
-from . import MixedBatch, HYGT_FORWARD, _abi
+from . import HYGT_FORWARD, _abi
 
 
 def _torch():
@@ -39,12 +46,13 @@ class Request:
     rid: int
     log2n: int
     x: object                 # [nblocks, N] float32, device
-    cls: object               # [nblocks] int32, device
+    cls: object               # [nblocks] int32, device (None when the size has one class)
     arrival: float            # host time (perf_counter seconds)
-    out: object = None        # [nblocks, N] float32, filled on completion
+    out: object = None        # [nblocks, N] float32, device; allocated by submit() if None
     ready: object = None      # optional event after which x and cls may be read
     done: float = None        # device completion time mapped to host seconds
     batch: int = -1           # index of the batch that served it
+    status: int = 0           # HYGT_OK, or HYGT_ECLASS (some block's class out of range)
 
     @property
     def nblocks(self) -> int:
@@ -54,62 +62,76 @@ class Request:
 @dataclass
 class _Slot:
     stream: object
-    x: dict
-    y: dict
-    cls: dict
-    workspace: object
     handle: int = 0           # the stream's HIP handle
     start: object = None      # events of the batch in flight, reused batch after batch
     event: object = None
     requests: list = field(default_factory=list)
+    entries: list = field(default_factory=list)   # ring indices of those requests
+    first: int = 0            # ring position (monotone) of the batch's first entry
+    batch: int = -1           # index of the batch in flight
     busy: bool = False
 
 
 class Server:
-    """tables: {log2n: angles [C, R, log2n, N/2] float32 on the device};
-    capacity: {log2n: blocks a slot can hold} (the memory cap);
-    slots: batches in flight at once."""
+    """tables: {log2n: angles [C, R, log2n, N/2] float32 on the device}, at
+    most four block sizes; capacity: {log2n: blocks one batch may hold} (the
+    memory cap of a batch); slots: batches in flight at once; ring: request
+    descriptors that may be queued or in flight at once."""
 
-    def __init__(self, tables: dict, capacity: dict, slots: int = 3, config: int | None = None):
+    def __init__(self, tables: dict, capacity: dict, slots: int = 3, ring: int = 4096,
+                 direction: int = HYGT_FORWARD):
+        import numpy as np
+
         torch = _torch()
-        self.tables = dict(tables)
-        self.sizes = sorted(self.tables, reverse=True)
+        if not 1 <= len(tables) <= _abi.HYGT_MAX_TABLES:
+            raise ValueError(f"1 to {_abi.HYGT_MAX_TABLES} block sizes")
+        self.sizes = sorted(tables)
         self.capacity = {d: int(capacity[d]) for d in self.sizes}
-        self.device = next(iter(self.tables.values())).device
+        self.device = tables[self.sizes[0]].device
+        self.direction = direction
         dev = self.device
-        seg_items = []
-        for d in self.sizes:
-            a = self.tables[d]
-            seg_items.append((0, 0, 0, 0, self.capacity[d], d, int(a.shape[1]), int(a.shape[0])))
-        ws_bytes = _abi.hygt_mixed_workspace_bytes(_abi.segments(seg_items), len(seg_items))
-        # a zero-copy batch: up to HYGT_MAX_SEGMENTS requests of any sizes,
-        # each at most its size's capacity
-        for d in self.sizes:
-            a = self.tables[d]
-            direct = [(0, 0, 0, 0, self.capacity[d], d, int(a.shape[1]),
-                       int(a.shape[0]))] * _abi.HYGT_MAX_SEGMENTS
-            ws_bytes = max(ws_bytes, _abi.hygt_mixed_workspace_bytes(_abi.segments(direct),
-                                                                     len(direct)))
+        # per-size multiplier tables, built once
+        self.mult, refs, self.nclasses = {}, [], {}
+        with torch.cuda.device(dev):
+            st = torch.cuda.current_stream(dev).cuda_stream
+            for d in self.sizes:
+                a = tables[d]
+                if not (a.is_cuda and a.dtype == torch.float32 and a.dim() == 4 and
+                        a.is_contiguous() and int(a.shape[2]) == d):
+                    raise ValueError(f"angles of log2n = {d} must be [C, R, {d}, N/2] float32")
+                nclasses, rounds = int(a.shape[0]), int(a.shape[1])
+                nbytes = _abi.hygt_table_bytes(d, rounds, nclasses)
+                if nbytes == 0:
+                    raise ValueError(f"unsupported sizes for log2n = {d}")
+                t = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                _abi._check(_abi.hygt_table_build(a.data_ptr(), d, rounds, nclasses,
+                                                  t.data_ptr(), nbytes, st), "hygt_table_build")
+                self.mult[d] = t
+                self.nclasses[d] = nclasses
+                refs.append((t.data_ptr(), d, rounds, nclasses))
+            torch.cuda.synchronize(dev)
+        self._tables = _abi.table_refs(refs)
+        self._tindex = {d: i for i, d in enumerate(self.sizes)}
+        # the descriptor ring, in pinned host memory that the device reads
+        self.ring_size = int(ring)
+        self._ring_mem = torch.empty(self.ring_size * _abi.REQUEST_BYTES, dtype=torch.uint8,
+                                     pin_memory=True)
+        self.ring = self._ring_mem.numpy().view(np.dtype(_abi.REQUEST_FIELDS))
+        self._ring_ptr = self._ring_mem.data_ptr()
+        self.tail = 0             # ring position of the next submitted request
+        self.head = 0             # ring position of the next request to dispatch
+        self.queue = collections.deque()   # submitted, not yet dispatched (ring order)
         self.slots = []
         for _ in range(slots):
-            self.slots.append(_Slot(
-                stream=torch.cuda.Stream(device=dev),
-                x={d: torch.zeros(self.capacity[d], 1 << d, device=dev) for d in self.sizes},
-                y={d: torch.zeros(self.capacity[d], 1 << d, device=dev) for d in self.sizes},
-                cls={d: torch.zeros(self.capacity[d], dtype=torch.int32, device=dev)
-                     for d in self.sizes},
-                workspace=torch.empty(ws_bytes, dtype=torch.uint8, device=dev)))
-            self.slots[-1].handle = int(self.slots[-1].stream.cuda_stream)
-            self.slots[-1].start = torch.cuda.Event(enable_timing=True)
-            self.slots[-1].event = torch.cuda.Event(enable_timing=True)
-        self.ws_bytes = ws_bytes
-        self._meta = {d: (int(self.tables[d].data_ptr()), int(self.tables[d].shape[1]),
-                          int(self.tables[d].shape[0])) for d in self.sizes}
-        self.queue = collections.deque()
+            s = _Slot(stream=torch.cuda.Stream(device=dev))
+            s.handle = int(s.stream.cuda_stream)
+            s.start = torch.cuda.Event(enable_timing=True)
+            s.event = torch.cuda.Event(enable_timing=True)
+            self.slots.append(s)
         self.batches = 0
         self.busy_s = 0.0         # summed device time of the finished batches
+        self.batch_log = []       # (batch, device start, device end, requests) per finished batch
         self.dispatch_s = 0.0     # host time spent starting batches
-        self.config = self._tune() if config is None else config
         # device time origin: host time t0 <-> event e0
         torch.cuda.synchronize(dev)
         self._e0 = torch.cuda.Event(enable_timing=True)
@@ -117,33 +139,51 @@ class Server:
         torch.cuda.synchronize(dev)
         self._t0 = time.perf_counter()
 
-    def _tune(self) -> int:
-        """Autotunes the mixed launch on a full slot."""
-        s = self.slots[0]
-        segs = [(s.x[d], s.y[d], s.cls[d], self.tables[d]) for d in self.sizes]
-        mb = MixedBatch(segs, stream=s.stream, workspace=s.workspace)
-        cfg, _ = mb.autotune(HYGT_FORWARD, stream=s.stream)
-        _torch().cuda.synchronize(self.device)
-        return cfg
+    def _oldest_live(self) -> int:
+        """Ring position of the oldest entry still queued or in flight."""
+        live = [s.first for s in self.slots if s.busy]
+        return min(live + [self.head])
 
     def submit(self, req: Request) -> None:
-        """Queues a request. Its x and cls must be complete on the device, or
-        req.ready must be an event recorded after the work that writes them
-        (the batch's stream then waits for it). The server keeps the request,
-        and so its tensors, until its batch has finished."""
-        if req.log2n not in self.tables:
-            raise ValueError(f"no angle table for log2n = {req.log2n}")
-        if req.nblocks > self.capacity[req.log2n]:
-            raise ValueError("request larger than a slot's capacity")
+        """Queues a request: checks it, allocates its output (unless given)
+        and writes its descriptor into the ring. Its x and cls must be complete
+        on the device, or req.ready must be an event recorded after the work
+        that writes them (the batch's stream then waits for it). The server
+        keeps the request, and so its tensors, until its batch has finished."""
         torch = _torch()
+        d = req.log2n
+        if d not in self._tindex:
+            raise ValueError(f"no angle table for log2n = {d}")
+        if req.nblocks > self.capacity[d]:
+            raise ValueError("request larger than a batch's capacity")
         x, c = req.x, req.cls
         if not (isinstance(x, torch.Tensor) and x.device == self.device and
-                x.dtype == torch.float32 and x.dim() == 2 and x.shape[1] == 1 << req.log2n and
+                x.dtype == torch.float32 and x.dim() == 2 and x.shape[1] == 1 << d and
                 x.is_contiguous()):
             raise ValueError("x must be a contiguous [B, N] float32 tensor on the server's device")
-        if not (isinstance(c, torch.Tensor) and c.device == self.device and
-                c.dtype == torch.int32 and c.shape == (x.shape[0],) and c.is_contiguous()):
+        if c is None:
+            if self.nclasses[d] != 1:
+                raise ValueError("cls may be None only for a size with one class")
+        elif not (isinstance(c, torch.Tensor) and c.device == self.device and
+                  c.dtype == torch.int32 and c.shape == (x.shape[0],) and c.is_contiguous()):
             raise ValueError("cls must be a contiguous [B] int32 tensor on the server's device")
+        if req.out is None:
+            req.out = torch.empty_like(x)
+        elif not (isinstance(req.out, torch.Tensor) and req.out.shape == x.shape and
+                  req.out.dtype == x.dtype and req.out.device == x.device and
+                  req.out.is_contiguous()):
+            raise ValueError("out must match x")
+        if self.tail - self._oldest_live() >= self.ring_size:
+            raise RuntimeError("request ring full: poll() until batches finish")
+        e = self.ring[self.tail % self.ring_size]
+        e["x"] = x.data_ptr()
+        e["y"] = req.out.data_ptr()
+        e["cls"] = 0 if c is None else c.data_ptr()
+        e["nblocks"] = req.nblocks
+        e["table"] = self._tindex[d]
+        e["status"] = 0
+        e["first_wg"] = 0
+        self.tail += 1
         self.queue.append(req)
 
     def _device_time(self, ev) -> float:
@@ -155,9 +195,13 @@ class Server:
         for s in self.slots:
             if s.busy and s.event.query():
                 t = self._device_time(s.event)
-                self.busy_s += s.start.elapsed_time(s.event) / 1e3
-                for r in s.requests:
+                t_start = self._device_time(s.start)
+                self.busy_s += t - t_start
+                self.batch_log.append((s.batch, t_start, t, len(s.requests)))
+                status = self.ring["status"]
+                for r, i in zip(s.requests, s.entries):
                     r.done = t
+                    r.status = int(status[i])
                 completed += len(s.requests)
                 s.requests = []
                 s.busy = False
@@ -171,60 +215,33 @@ class Server:
         return completed
 
     def _dispatch(self, s: _Slot) -> None:
-        torch = _torch()
-        used = {d: 0 for d in self.sizes}
+        used = dict.fromkeys(self.sizes, 0)
         taken = []
-        while self.queue:
+        while self.queue and len(taken) < _abi.HYGT_MAX_BATCH_REQUESTS:
             r = self.queue[0]
             if used[r.log2n] + r.nblocks > self.capacity[r.log2n]:
                 break          # first come, first served: the head waits for the next slot
             self.queue.popleft()
-            taken.append((r, used[r.log2n]))
+            taken.append(r)
             used[r.log2n] += r.nblocks
         if not taken:
             return
-        direct = len(taken) <= _abi.HYGT_MAX_SEGMENTS
-        with torch.cuda.stream(s.stream):
-            s.start.record(s.stream)
-            for r, _ in taken:
-                if r.ready is not None:
-                    s.stream.wait_event(r.ready)
-                r.out = torch.empty_like(r.x)
-                r.batch = self.batches
-            if direct:
-                self._launch(s, [(r.x.data_ptr(), r.out.data_ptr(), r.cls.data_ptr(),
-                                  r.nblocks, r.log2n) for r, _ in taken])
-            else:
-                self._gathered(s, taken, used)
-            s.event.record(s.stream)
-        s.requests = [r for r, _ in taken]
+        s.start.record(s.stream)
+        for r in taken:
+            if r.ready is not None:
+                s.stream.wait_event(r.ready)
+            r.batch = self.batches
+        st = _abi.hygt_requests_apply(self._ring_ptr, self.ring_size, self.head, len(taken),
+                                      self._tables, len(self.sizes), self.direction, s.handle)
+        _abi._check(st, "hygt_requests_apply")
+        s.event.record(s.stream)
+        s.requests = taken
+        s.entries = [(self.head + i) % self.ring_size for i in range(len(taken))]
+        s.first = self.head
+        s.batch = self.batches
         s.busy = True
+        self.head += len(taken)
         self.batches += 1
-
-    def _gathered(self, s: _Slot, taken: list, used: dict) -> None:
-        """More requests than one launch has segments: gathered per size into
-        the slot's buffers, transformed, copied out."""
-        for r, off in taken:
-            s.x[r.log2n][off:off + r.nblocks].copy_(r.x, non_blocking=True)
-            s.cls[r.log2n][off:off + r.nblocks].copy_(r.cls, non_blocking=True)
-        self._launch(s, [(s.x[d].data_ptr(), s.y[d].data_ptr(), s.cls[d].data_ptr(), used[d], d)
-                         for d in self.sizes if used[d] > 0])
-        for r, off in taken:
-            r.out.copy_(s.y[r.log2n][off:off + r.nblocks], non_blocking=True)
-
-    def _launch(self, s: _Slot, parts: list) -> None:
-        """Plan + one mixed launch on the slot's stream over (x, y, cls,
-        nblocks, log2n) segments whose tensors submit() has checked."""
-        items = []
-        for x, y, c, nb, d in parts:
-            ang, rounds, nclasses = self._meta[d]
-            items.append((x, y, c, ang, nb, d, rounds, nclasses))
-        segs = _abi.segments(items)
-        ws = s.workspace.data_ptr()
-        _abi._check(_abi.hygt_mixed_plan(segs, len(items), ws, self.ws_bytes, s.handle),
-                    "hygt_mixed_plan")
-        _abi._check(_abi.hygt_mixed_apply(segs, len(items), HYGT_FORWARD, self.config, ws,
-                                          self.ws_bytes, s.handle), "hygt_mixed_apply")
 
     def drain(self) -> None:
         while self.queue or any(s.busy for s in self.slots):
@@ -252,12 +269,28 @@ def run_poisson(server: Server, requests: list, rate: float, seed: int = 4) -> d
     lat = np.array([r.done - r.arrival for r in requests]) * 1e3
     blocks = sum(r.nblocks for r in requests)
     busy = server.busy_s
+    per_batch = collections.Counter(r.batch for r in requests)
     return {"requests": len(requests), "blocks": blocks, "batches": server.batches,
+            "max_requests_per_batch": max(per_batch.values()),
+            "overlapping_batches": overlapping_batches(server.batch_log),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
             "blocks_per_s": blocks / (t_end - t_start), "wall_s": t_end - t_start,
             "device_busy_s": busy, "offered_rate": rate,
             "host_dispatch_us_per_batch": 1e6 * server.dispatch_s / max(server.batches, 1)}
+
+
+def overlapping_batches(log: list) -> int:
+    """Batches whose device interval (start, end) overlaps another batch's."""
+    spans = sorted((a, b) for _, a, b, _ in log)
+    hit = [False] * len(spans)
+    end, who = float("-inf"), -1
+    for i, (a, b) in enumerate(spans):
+        if a < end:
+            hit[i] = hit[who] = True
+        if b > end:
+            end, who = b, i
+    return sum(hit)
 
 
 # Size mix of the serving workload: 4x4 : 8x8 : 16x16 blocks = 8 : 4 : 1.

@@ -242,3 +242,80 @@ def test_noalloc_rejects_sizes_beyond_its_area():
     assert "static scratch area" in _abi.strerror(st)
     # sizes out of range
     assert _abi.hygt_transform_noalloc(0, 0, 0, 16, 9, 4, 0, 35, 0, 0) == _abi.HYGT_EINVAL
+
+
+def test_table_bytes_and_build_rejects():
+    n = _abi.hygt_table_bytes(6, 4, 35)
+    # modes [2][C] int32, coef [2][C][R*d][N] float, signs [2][C][N] float, each 256-aligned
+    up = lambda v: (v + 255) // 256 * 256
+    assert n == up(up(up(2 * 35 * 4) + 2 * 35 * 24 * 64 * 4) + 2 * 35 * 64 * 4)
+    for bad in ((1, 4, 35), (9, 4, 35), (6, 0, 35), (6, 65, 35), (6, 4, 0), (6, 4, 4097)):
+        assert _abi.hygt_table_bytes(*bad) == 0, bad
+    tb = _abi.hygt_table_build
+    assert tb(FAKE, 1, 4, 35, FAKE, 1 << 30, 0) == _abi.HYGT_EINVAL          # N = 2
+    assert tb(0, 6, 4, 35, FAKE, n, 0) == _abi.HYGT_EINVAL                   # NULL angles
+    assert tb(FAKE, 6, 4, 35, FAKE, n - 1, 0) == _abi.HYGT_EWORKSPACE        # too small
+    assert tb(FAKE, 6, 4, 35, FAKE + 16, n, 0) == _abi.HYGT_EWORKSPACE       # misaligned
+    assert tb(FAKE, 6, 4, 35, 0, n, 0) == _abi.HYGT_EWORKSPACE               # NULL table
+
+
+def _ring(entries):
+    import numpy as np
+
+    ring = np.zeros(len(entries), dtype=np.dtype(_abi.REQUEST_FIELDS))
+    assert ring.itemsize == _abi.REQUEST_BYTES
+    for i, (x, y, c, nb, t) in enumerate(entries):
+        ring[i] = (x, y, c, nb, t, 0, -7)
+    return ring
+
+
+def test_requests_apply_rejects_on_the_host():
+    import ctypes
+
+    assert _abi.HYGT_MAX_REQUEST_BLOCKS == 1 << 26
+    tabs = _abi.table_refs([(FAKE, 4, 2, 3), (FAKE * 2, 6, 4, 1)])
+    good = (FAKE * 4, FAKE * 8, FAKE * 16, 100, 0)
+    ap = _abi.hygt_requests_apply
+
+    def call(entries, first=0, count=None, tables=tabs, ntables=2, direction=0, cap=None):
+        ring = _ring(entries)
+        n = len(entries) if count is None else count
+        c = len(entries) if cap is None else cap
+        st = ap(ring.ctypes.data, c, first, n, tables, ntables, direction, 0)
+        return st, ring
+
+    # every failing entry is found before anything is written or launched
+    cases = {
+        "table index": [good, (FAKE * 4, FAKE * 8, FAKE * 16, 100, 2)],
+        "negative table": [(FAKE * 4, FAKE * 8, FAKE * 16, 100, -1)],
+        "negative blocks": [(FAKE * 4, FAKE * 8, FAKE * 16, -1, 0)],
+        "too many blocks": [(FAKE * 4, FAKE * 8, FAKE * 16, (1 << 26) + 1, 0)],
+        "NULL x": [(0, FAKE * 8, FAKE * 16, 100, 0)],
+        "misaligned y": [(FAKE * 4, FAKE * 8 + 4, FAKE * 16, 100, 0)],
+        "NULL cls, 3 classes": [(FAKE * 4, FAKE * 8, 0, 100, 0)],
+        "misaligned cls": [(FAKE * 4, FAKE * 8, FAKE * 16 + 2, 100, 0)],
+        "partial overlap": [(FAKE * 4, FAKE * 4 + 64, FAKE * 16, 100, 0)],
+    }
+    for what, entries in cases.items():
+        st, ring = call(entries)
+        assert st == _abi.HYGT_EINVAL, what
+        assert (ring["first_wg"] == -7).all(), what      # nothing written
+    assert call([good], direction=2)[0] == _abi.HYGT_EINVAL
+    assert call([good], count=0)[0] == _abi.HYGT_EINVAL
+    assert call([good] * 65, count=65)[0] == _abi.HYGT_EINVAL      # over the batch limit
+    assert call([good], count=2)[0] == _abi.HYGT_EINVAL            # more than the ring
+    assert call([good], first=-1)[0] == _abi.HYGT_EINVAL
+    assert call([good], ntables=0)[0] == _abi.HYGT_EINVAL
+    assert call([good], ntables=5)[0] == _abi.HYGT_EINVAL
+    bad_tab = _abi.table_refs([(FAKE + 16, 4, 2, 3)])              # misaligned table
+    assert call([good], tables=bad_tab, ntables=1)[0] == _abi.HYGT_EINVAL
+    bad_tab = _abi.table_refs([(FAKE, 1, 2, 3)])                   # N = 2
+    assert call([good], tables=bad_tab, ntables=1)[0] == _abi.HYGT_EINVAL
+    assert ap(0, 1, 0, 1, tabs, 2, 0, 0) == _abi.HYGT_EINVAL       # NULL ring
+    # requests without blocks launch nothing, but get their first workgroup
+    empty = (0, 0, 0, 0, 0)
+    st, ring = call([empty, empty, (0, 0, 0, 0, 1)], first=5)
+    assert st == _abi.HYGT_OK and (ring["first_wg"] == 0).all()
+    # one class: cls may be NULL (checked only; this call does launch, so it
+    # is not made here)
+    assert ctypes.sizeof(_abi.TableRef) == 24
