@@ -365,6 +365,7 @@ def _cpu_baseline(x, cls, ang, sample):
         done = sum(pool.map(_oracle_fwd_inv, parts))
         dtp = time.perf_counter() - t0
     return {"value": done / dtp, "unit": "blocks/s", "cores": len(parts), "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": f"{len(parts)} processes, each forward + inverse of {sample} consecutive "
                       f"blocks of the batch ({done} blocks, {dtp:.1f} s), FP64 NumPy",
             "single_process_value": sample / dt1,
@@ -379,6 +380,65 @@ def _copy_ceiling(torch, xs, out, steps):
         out.copy_(xs[k % len(xs)])
     ms = _avg_ms(torch, lambda i: out.copy_(xs[i % len(xs)]), steps)
     return {"ms": ms, "gbps": 2 * out.numel() * 4 / (ms / 1e3) / 1e9}
+
+
+def _ceiling_lib():
+    import ctypes
+
+    from paper_2505_21728_amd import build
+
+    if not os.path.exists(build.BENCH_LIB):
+        raise ImportError(f"{build.BENCH_LIB} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(build.BENCH_LIB)
+    c = ctypes
+    lib.hygt_ceiling_stream_copy.restype = c.c_int
+    lib.hygt_ceiling_stream_copy.argtypes = [c.c_void_p, c.c_void_p, c.c_int64, c.c_void_p]
+    lib.hygt_ceiling_gather_copy.restype = c.c_int
+    lib.hygt_ceiling_gather_copy.argtypes = [c.c_void_p, c.c_void_p, c.c_int64, c.c_int, c.c_int,
+                                             c.c_int, c.c_void_p, c.c_size_t, c.c_void_p]
+    return lib
+
+
+def _ceilings(torch, plans, xs, out, steps):
+    """Memory ceilings of the forward launch, timed like it (back-to-back
+    launches over the input ring between two events on the main stream):
+    a streaming copy of the batch (contiguous 16 KB pieces, 16-byte loads and
+    non-temporal stores), and a gathered copy: the rotation kernel's own
+    loads and stores (the plan's class-grouped tiles, LDS DMA tile load,
+    LDS-staged whole-block stores) with the passes taken out."""
+    lib = _ceiling_lib()
+    st = torch.cuda.current_stream().cuda_stream
+    nbytes = 2 * out.numel() * 4
+
+    def stream(i):
+        assert lib.hygt_ceiling_stream_copy(xs[i % len(xs)].data_ptr(), out.data_ptr(),
+                                            out.numel(), st) == 0
+
+    def gather(i):
+        p = plans[i % len(plans)]
+        assert lib.hygt_ceiling_gather_copy(xs[i % len(xs)].data_ptr(), out.data_ptr(),
+                                            p.nblocks, p.log2n, p.rounds, p.nclasses,
+                                            p.workspace.data_ptr(), p.ws_bytes, st) == 0
+
+    res = {}
+    for name, fn in (("stream_copy", stream), ("gather_copy", gather)):
+        for i in range(3):
+            fn(i)
+        ms = _avg_ms(torch, fn, steps)
+        res[name] = {"ms": ms, "gbps": nbytes / (ms / 1e3) / 1e9}
+    return res
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def _pcts(vals):
@@ -428,17 +488,29 @@ def main():
     main = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def run_steps(nsteps):
-        """nsteps steps, each the whole path on batch k: plan, forward, inverse,
-        enqueued back to back on one stream with no host synchronisation."""
-        p = None
-        for k in range(nsteps):
-            p = hygt.Plan(at, cs[k % RING], workspace=ws, stream=main)
-            p.forward(xs[k % RING], out=yt, stream=main)
-            p.inverse(yt, out=zt, stream=main)
-        return p
+    from paper_2505_21728_amd import _abi
 
-    run_steps(max(args.warmup, 1)).check()
+    handle = main.cuda_stream
+    xp = [t.data_ptr() for t in xs]
+    cp = [t.data_ptr() for t in cs]
+    ap, yp, zp, wp = at.data_ptr(), yt.data_ptr(), zt.data_ptr(), ws.data_ptr()
+
+    def run_steps(nsteps):
+        """nsteps steps, each the whole path on batch k through the C ABI:
+        hygt_plan, hygt_apply forward, hygt_apply inverse, enqueued back to
+        back on one stream with no host synchronisation."""
+        for k in range(nsteps):
+            b = k % RING
+            st = _abi.hygt_plan(cp[b], NBLOCKS, LOG2N, ROUNDS, ap, NCLASSES, wp, wsb, handle)
+            st |= _abi.hygt_apply(xp[b], yp, NBLOCKS, LOG2N, ROUNDS, NCLASSES, _abi.HYGT_FORWARD,
+                                  wp, wsb, handle)
+            st |= _abi.hygt_apply(yp, zp, NBLOCKS, LOG2N, ROUNDS, NCLASSES, _abi.HYGT_INVERSE,
+                                  wp, wsb, handle)
+            if st != _abi.HYGT_OK:
+                raise RuntimeError(f"step {k}: status {st}")
+
+    run_steps(max(args.warmup, 1))
+    _abi._check(_abi.hygt_check_error(wp, wsb, handle), "hygt_check_error")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_steps(args.steps)
@@ -469,6 +541,7 @@ def main():
     step_gbps = 2 * launch_bytes / (ms_per_step / 1e3) / 1e9
 
     copy = _copy_ceiling(torch, xs, zt, args.steps)
+    ceil = _ceilings(torch, plans, xs, zt, args.steps)
     klt = variants = grad = mixed = served = None
     if not args.main_only:
         klt = _klt_comparison(torch, hygt, at, cs, xs, args.steps)
@@ -499,10 +572,13 @@ def main():
         "fwd_ms": fwd_ms,
         "inv_ms": inv_ms,
         "copy_ceiling": copy,
+        "ceilings": ceil,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": _measured_traffic(),
                      "frac_of_copy_ceiling": achieved / copy["gbps"],
+                     "fwd_vs_stream_copy_time": ceil["stream_copy"]["ms"] / fwd_ms,
+                     "fwd_vs_gather_copy_time": ceil["gather_copy"]["ms"] / fwd_ms,
                      "kernel": "rotate_kernel<6,0,4> (forward)",
                      "bytes_per_launch": launch_bytes,
                      "flops_per_launch": NBLOCKS * FLOPS_PER_BLOCK},

@@ -331,9 +331,13 @@ int hygt_graph_destroy(hygt_graph graph);
  * frames, Sec. VI: blocks of one size each, with a class per block), where
  * latency rather than bulk throughput matters. The multiplier tables of each
  * block size are built once (hygt_table_build()) and stay on the device. The
- * requests themselves are descriptors in a ring that the caller fills and the
- * device reads: one launch (hygt_requests_apply()) transforms a run of
+ * requests themselves are descriptors in a ring in pinned host memory that
+ * the caller fills: one launch (hygt_requests_apply()) transforms a run of
  * consecutive ring entries, with no plan, no workspace and no class grouping.
+ * The call hands the run's descriptors to the launch with its arguments (so
+ * that no wavefront reads host memory: such reads cost about 0.1 us each,
+ * one after another, which for a launch of 512 workgroups took 1.3 ms), and
+ * the device writes each request's status back into its ring entry.
  * Each lane takes one block and follows its own class's table (the
  * multipliers arrive by vector loads, not as wave-uniform scalars), so a
  * block's arithmetic, and so its result, is bit for bit that of
@@ -382,15 +386,14 @@ typedef struct hygt_request {
 /* Transforms requests ring[(first + i) % capacity], i = 0 .. count - 1
  * (1 <= count <= HYGT_MAX_BATCH_REQUESTS), forward or inverse, in one launch
  * on `stream`.
- *   ring    capacity entries in pinned host memory that the device can read
- *           and write (hipHostMalloc), 8-byte aligned; other memory is
- *           rejected with HYGT_EINVAL (hipHostGetDevicePointer gives the
- *           device's address of the ring). The host part of this call
- *           reads each entry's sizes and writes its first_wg; the device
- *           reads the entries' descriptors and, for a request with a class
- *           out of range, writes its status. So the `count` entries must not
- *           be rewritten, and their status read, before the stream has
- *           passed the end of this call's work.
+ *   ring    capacity entries in pinned host memory that the device can
+ *           write (hipHostMalloc), 8-byte aligned; other memory is rejected
+ *           with HYGT_EINVAL (hipHostGetDevicePointer gives the device's
+ *           address of the ring). The host part of this call reads the
+ *           entries (they may be rewritten as soon as it returns) and writes
+ *           their first_wg; the device writes the status of a request with a
+ *           class out of range, so the statuses are final once the stream
+ *           has passed the end of this call's work.
  *   tables  ntables (1 .. HYGT_MAX_TABLES) table references, host memory,
  *           read during the call; the tables themselves must stay until
  *           the work ends.
@@ -407,7 +410,10 @@ int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int
 /* Waits for `stream`, then reports whether the last non-empty plan on this
  * workspace met a class index outside [0, nclasses) (HYGT_ECLASS), a HIP
  * error (HYGT_EHIP), or neither (HYGT_OK). Reads at most workspace_bytes
- * bytes of the workspace. */
+ * bytes of the workspace. A plan of zero blocks launches nothing and writes
+ * nothing, so on a workspace (or a mixed batch's part) that has only seen
+ * such plans the answer is undefined: there is nothing to check, and the
+ * caller should not ask (the Python binding skips those parts). */
 int hygt_check_error(const void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* A static, human-readable description of a status code. */

@@ -229,6 +229,11 @@ class Plan:
     def check(self):
         """Synchronises and raises HygtError if a class index was out of range."""
         torch = _torch()
+        if self.nblocks == 0:
+            # a plan of no blocks writes nothing into the workspace
+            with torch.cuda.device(self.device):
+                torch.cuda.synchronize()
+            return
         with torch.cuda.device(self.device):
             st = _abi.hygt_check_error(self.workspace.data_ptr(), self.ws_bytes,
                                        _stream_handle(self._stream))
@@ -398,8 +403,9 @@ class MixedBatch:
         for x, ang in zip(self.x, self.angles):
             c, r, d, _ = (int(v) for v in ang.shape)
             part = workspace_bytes(x.shape[0], d, r, c)
-            st = _abi.hygt_check_error(self.workspace.data_ptr() + off, part, 0)
-            _abi._check(st, "hygt_check_error")
+            if x.shape[0] > 0:        # an empty segment's part is never written
+                st = _abi.hygt_check_error(self.workspace.data_ptr() + off, part, 0)
+                _abi._check(st, "hygt_check_error")
             off += (part + 255) // 256 * 256
 
 

@@ -20,6 +20,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhygt.so")
+# Memory-ceiling kernels for the benchmark, in a library of their own.
+BENCH_CSRC = os.path.join(PKG, "bench_csrc")
+BENCH_LIB = os.path.join(PKG, "libhygt_ceiling.so")
 
 ARCH = "gfx950"
 
@@ -52,11 +55,11 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found; the HyGT library needs ROCm's hipcc to build")
 
 
-def _sources() -> list[str]:
+def _sources(folder: str = CSRC) -> list[str]:
     out = []
-    for name in sorted(os.listdir(CSRC)):
+    for name in sorted(os.listdir(folder)):
         if name.endswith((".hip", ".cpp")):
-            out.append(os.path.join(CSRC, name))
+            out.append(os.path.join(folder, name))
     return out
 
 
@@ -73,21 +76,28 @@ def _compile(src: str, hipcc: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    """Compiles every source and links libhygt.so; returns the library path."""
-    hipcc = _hipcc()
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = _sources()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, hipcc), srcs))
-    tmp = LIB + ".tmp"
+def _link(objs: list[str], lib: str, hipcc: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = True) -> str:
+    """Compiles every source and links libhygt.so (and the benchmark's
+    libhygt_ceiling.so); returns the library path."""
+    hipcc = _hipcc()
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = _sources()
+    bench_srcs = _sources(BENCH_CSRC)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, hipcc), srcs + bench_srcs))
+    _link(objs[:len(srcs)], LIB, hipcc)
+    _link(objs[len(srcs):], BENCH_LIB, hipcc)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {BENCH_LIB}")
     return LIB
 
 

@@ -5,6 +5,7 @@
 #include "hygt.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdint>
 #include <new>
 #include <vector>
@@ -16,6 +17,8 @@ static_assert(HYGT_MAX_TABLES == hygt::kMaxReqTables, "table limits differ");
 static_assert(HYGT_MAX_BATCH_REQUESTS == hygt::kMaxBatchRequests && HYGT_MAX_BATCH_REQUESTS <= 64,
               "a batch's descriptors are read a lane each");
 static_assert(sizeof(hygt_request) == 48 && sizeof(hygt_table_ref) == 24, "descriptor layout");
+static_assert(offsetof(hygt_request, status) == 36, "a status every 12 int32 from entry 0's");
+static_assert(HYGT_MAX_REQUEST_BLOCKS <= (1LL << 26), "block counts and workgroups in int32");
 
 namespace {
 
@@ -563,10 +566,20 @@ int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int
         if (!overlap_ok(e.x, e.y, e.nblocks, t.log2n)) return HYGT_EINVAL;
         if (e.cls == nullptr ? t.nclasses != 1 : !aligned(e.cls, 4)) return HYGT_EINVAL;
     }
+    // The batch's descriptors go to the launch by value (the kernel reads
+    // them from its argument segment); only the statuses are written back
+    // into the ring by the device.
     int64_t wgs = 0;
     for (int i = 0; i < count; ++i) {
         hygt_request& e = ring[(first + i) % capacity];
         e.first_wg = wgs;
+        hygt::ReqDesc& q = a.req[i];
+        q.x = e.x;
+        q.y = e.y;
+        q.cls = e.cls;
+        q.nblocks = static_cast<int32_t>(e.nblocks);
+        q.table = e.table;
+        q.first_wg = static_cast<int32_t>(wgs);
         wgs += hygt::request_workgroups(e.nblocks, tables[e.table].log2n);
     }
     if (wgs == 0) return HYGT_OK;
@@ -577,7 +590,8 @@ int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int
         (void)hipGetLastError();  // clear the error this leaves behind
         return HYGT_EINVAL;
     }
-    a.ring = dring;
+    a.status = reinterpret_cast<int32_t*>(static_cast<char*>(dring) +
+                                          offsetof(hygt_request, status));
     a.capacity = capacity;
     a.first = first;
     a.count = count;

@@ -286,19 +286,34 @@ struct ReqTable {
     int pad;
 };
 
-// Arguments of a request launch (hygt_request.hip). `ring` points to
-// hygt_request entries (include/hygt.h), seen here as raw memory so that
-// this header needs no part of the public one.
+// One request of a launch, copied from its ring entry by the host.
+struct ReqDesc {
+    const float* x;
+    float* y;
+    const int32_t* cls;
+    int32_t nblocks;   // <= 2^26
+    int32_t table;
+    int32_t first_wg;  // first workgroup of the request in the launch
+    int32_t pad;
+};
+
+// Arguments of a request launch (hygt_rotate.hip): the batch's descriptors
+// travel with the launch, so that the kernel reads them from its argument
+// segment rather than from host memory; `status` is the device's address
+// of ring entry 0's status field (entries are 12 int32 apart), where a
+// request with a class out of range gets HYGT_ECLASS.
 constexpr int kMaxReqTables = 4;
 constexpr int kMaxBatchRequests = 64;
 struct RequestArgs {
-    void* ring;
+    int32_t* status;
     int64_t capacity;
-    int64_t first;
+    int64_t first;  // ring index of the batch's first entry (< capacity)
     int count;
     int ntables;
     ReqTable tab[kMaxReqTables];
+    ReqDesc req[kMaxBatchRequests];
 };
+static_assert(sizeof(RequestArgs) <= 4096, "kernel arguments");
 
 // Workgroups (of four wavefronts) of a request of nblocks blocks of 2^log2n
 // values: four tiles of 64 blocks per workgroup for N <= 64, two for

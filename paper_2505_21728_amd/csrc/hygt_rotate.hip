@@ -808,19 +808,27 @@ hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, i
 
 namespace {
 
-// A lane's own multiplier table, read with 16-byte vector loads two chunks
+// A lane's own multiplier table, read with 16-byte vector loads P chunks
 // ahead of their use. The lanes of a wavefront hold blocks of different
-// classes here, so the multipliers cannot be wave-uniform scalars. next()
-// passes the older chunk to an empty asm statement that also rewrites the
-// table address: the compiler waits for that chunk there (while the younger
-// one stays in flight), and the load issued next, addressed from the
-// rewritten value, cannot move above it.
-template <int F>
+// classes here, so the multipliers cannot be wave-uniform scalars, and a
+// small batch has too few wavefronts to hide the loads' latency with each
+// other: the stream keeps P chunks in flight. next() passes the oldest chunk
+// to an empty asm statement that also rewrites the table address: the
+// compiler waits for that chunk there (while the younger ones stay in
+// flight), and the load issued next, addressed from the rewritten value,
+// cannot move above it.
+#ifndef HYGT_LANE_PREFETCH
+#define HYGT_LANE_PREFETCH 3
+#endif
+constexpr int kLanePrefetch = HYGT_LANE_PREFETCH;
+
+template <int F, int P = kLanePrefetch>
 struct LaneStream {
     static_assert(F >= 4, "chunks of whole 16-byte loads");
+    static_assert(P >= 1, "chunks in flight");
     uint64_t base;
-    Chunk<F> c0, c1;  // requested, oldest first
-    __device__ __forceinline__ void load(Chunk<F>& c, int64_t off) {
+    Chunk<F> c[P];  // requested, oldest first
+    __device__ __forceinline__ void load(Chunk<F>& ch, int64_t off) {
         constexpr int W = Chunk<F>::W;
         // global (not generic) loads: they count only against vmcnt
         typedef float vf4 __attribute__((ext_vector_type(4)));
@@ -829,26 +837,30 @@ struct LaneStream {
         StaticFor<0, F / 4>::run([&](auto kk) {
             constexpr int k = decltype(kk)::value;
             const vf4 f = p[k];
-            c.a[(4 * k) / W][(4 * k) % W] = f.x;
-            c.a[(4 * k + 1) / W][(4 * k + 1) % W] = f.y;
-            c.a[(4 * k + 2) / W][(4 * k + 2) % W] = f.z;
-            c.a[(4 * k + 3) / W][(4 * k + 3) % W] = f.w;
+            ch.a[(4 * k) / W][(4 * k) % W] = f.x;
+            ch.a[(4 * k + 1) / W][(4 * k + 1) % W] = f.y;
+            ch.a[(4 * k + 2) / W][(4 * k + 2) % W] = f.z;
+            ch.a[(4 * k + 3) / W][(4 * k + 3) % W] = f.w;
         });
     }
-    __device__ __forceinline__ void begin(const float* table, int64_t off0, int64_t off1) {
+    // Requests the first P chunks, at offset_of(i) for i = 0 .. P-1.
+    template <class OffsetOf>
+    __device__ __forceinline__ void begin(const float* table, OffsetOf&& offset_of) {
         base = reinterpret_cast<uint64_t>(table);
-        load(c0, off0);
-        load(c1, off1);
+        StaticFor<0, P>::run([&](auto ii) { load(c[decltype(ii)::value], offset_of(ii)); });
     }
     // Returns the oldest requested chunk and requests the one at `off`.
     __device__ __forceinline__ Chunk<F> next(int64_t off) {
         if constexpr (Chunk<F>::NV == 1)
-            asm volatile("" : "+v"(base) : "v"(c0.a[0]));
+            asm volatile("" : "+v"(base) : "v"(c[0].a[0]));
         else
-            asm volatile("" : "+v"(base) : "v"(c0.a[0]), "v"(c0.a[1]));
-        const Chunk<F> got = c0;
-        c0 = c1;
-        load(c1, off);
+            asm volatile("" : "+v"(base) : "v"(c[0].a[0]), "v"(c[0].a[1]));
+        const Chunk<F> got = c[0];
+        StaticFor<0, P - 1>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            c[i] = c[i + 1];
+        });
+        load(c[P - 1], off);
         return got;
     }
 };
@@ -863,14 +875,18 @@ __device__ __forceinline__ void lane_rounds(float (&v)[1 << D], const float* tbl
     constexpr int CPR = D * CPP;
     const int64_t last = static_cast<int64_t>(rounds) * CPR - 1;  // index of the last chunk
     LaneStream<F> ls;
-    ls.begin(tbl, 0, last >= 1 ? F : 0);
+    constexpr int P = kLanePrefetch;
+    ls.begin(tbl, [&](auto ii) -> int64_t {
+        constexpr int i = decltype(ii)::value;
+        return (i <= last ? i : last) * F;
+    });
     for (int r = 0; r < rounds; ++r) {
         StaticFor<0, CPR>::run([&](auto ee) {
             constexpr int e = decltype(ee)::value;
             constexpr int kk = e / CPP;
             constexpr int H = e % CPP;
             constexpr int K = DIR == 0 ? kk : D - 1 - kk;
-            const int64_t ahead = static_cast<int64_t>(r) * CPR + e + 2;
+            const int64_t ahead = static_cast<int64_t>(r) * CPR + e + P;
             const Chunk<F> m = ls.next((ahead <= last ? ahead : last) * F);
             lift_chunk<D, K, H, F>(v, m);
         });
@@ -910,9 +926,11 @@ __device__ __forceinline__ void lane_passes_split(float (&v)[64], const float* t
         constexpr int kk = split_chunk_pass<D, DIR>(J);
         return split_first<D, DIR>(r, kk, q) + 32 * (J - split_chunks_before<D, DIR>(kk));
     };
-    // the chunk two after chunk J of round r (past the last: the last again)
+    // the chunk P after chunk J of round r (past the last: the last again)
+    constexpr int P = kLanePrefetch;
+    static_assert(P <= CR, "prefetch within the next round");
     auto ahead = [&](int64_t r, auto jj) -> int64_t {
-        constexpr int J = decltype(jj)::value + 2;
+        constexpr int J = decltype(jj)::value + P;
         if constexpr (J < CR) {
             return off_of(r, std::integral_constant<int, J>{});
         } else {
@@ -921,8 +939,8 @@ __device__ __forceinline__ void lane_passes_split(float (&v)[64], const float* t
         }
     };
     LaneStream<32> ls;
-    ls.begin(tbl, off_of(0, std::integral_constant<int, 0>{}),
-             off_of(0, std::integral_constant<int, 1>{}));
+    // the first P chunks of round 0 (CR >= P: no round holds fewer)
+    ls.begin(tbl, [&](auto ii) -> int64_t { return off_of(0, ii); });
     for (int r = 0; r < rounds; ++r) {
         StaticFor<0, D>::run([&](auto kk) {
             constexpr int k = decltype(kk)::value;
@@ -976,6 +994,8 @@ __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __
     if (blk >= 0 && cls != nullptr) c = cls[blk];
     const bool bad = blk >= 0 && (c < 0 || c >= tb.nclasses);
     if (bad) {
+        // the ring is in host memory: a system-scope store, which no cache
+        // between the device and that memory holds back
         __hip_atomic_store(status, static_cast<int32_t>(HYGT_ECLASS), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
         c = 0;
@@ -1020,97 +1040,52 @@ __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __
 // be global (made from the integer as a global pointer, then converted), so
 // that every access derived from it is a global rather than a generic
 // (flat) load or store.
-// The ring lives in host memory, written by the host between launches:
-// its fields are read, and the status written, at system scope, so that no
-// cache between the device and host memory can hold a stale copy whatever
-// the coherence of the host allocation.
-template <typename T>
-__device__ __forceinline__ T ring_load(T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 template <typename T>
 __device__ __forceinline__ T* global_ptr(uint64_t u) {
     typedef __attribute__((address_space(1))) T* G;
     return (T*)reinterpret_cast<G>(u);
 }
 
-__device__ __forceinline__ uint64_t read_lane64(uint64_t v, int l) {
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(v), l);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), l);
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-// Table ti of the launch, field by field as masked ORs of the wave-uniform
-// arguments: selects would be folded back into an access of the argument
-// array at a run-time index, which the compiler serves from a copy of the
-// arguments in scratch memory.
-__device__ __forceinline__ ReqTable pick_table(const RequestArgs& a, int ti) {
-    uint64_t modes = 0, coef = 0, signs = 0;
-    int log2n = 0, rounds = 0, nclasses = 0;
-    StaticFor<0, kMaxReqTables>::run([&](auto kk) {
-        constexpr int k = decltype(kk)::value;
-        const uint64_t m = 0 - static_cast<uint64_t>(ti == k);
-        const int mi = static_cast<int>(m);
-        modes |= reinterpret_cast<uint64_t>(a.tab[k].modes) & m;
-        coef |= reinterpret_cast<uint64_t>(a.tab[k].coef) & m;
-        signs |= reinterpret_cast<uint64_t>(a.tab[k].signs) & m;
-        log2n |= a.tab[k].log2n & mi;
-        rounds |= a.tab[k].rounds & mi;
-        nclasses |= a.tab[k].nclasses & mi;
-    });
-    ReqTable t;
-    t.modes = reinterpret_cast<const int32_t*>(modes);
-    t.coef = reinterpret_cast<const float*>(coef);
-    t.signs = reinterpret_cast<const float*>(signs);
-    t.log2n = log2n;
-    t.rounds = rounds;
-    t.nclasses = nclasses;
-    t.pad = 0;
-    return t;
-}
-
 // Workgroup w belongs to the last of the batch's requests whose first
 // workgroup is <= w (first_wg is non-decreasing along the batch, and a
-// request without blocks shares its first workgroup with the next one).
-// Lane i of every wavefront reads entry i's descriptor, so the batch costs
-// one round trip to the ring; the chosen request's fields are then read
-// from its lane.
+// request without blocks shares its first workgroup with the next one),
+// found by a binary search over the descriptors in the kernel's argument
+// segment (wave-uniform scalar loads).
 template <int DIR>
 __global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
     __shared__ float4 lds[4][512];
+    typedef const __attribute__((address_space(4))) RequestArgs* ArgPtr;
+    const ArgPtr pa = (ArgPtr)__builtin_amdgcn_kernarg_segment_ptr();
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t w = blockIdx.x;
-    hygt_request* ring = static_cast<hygt_request*>(a.ring);
-    int64_t idx = 0, fw = INT64_MAX, nb = 0;
-    uint64_t ex = 0, ey = 0, ec = 0;
-    int et = 0;
-    if (lane < a.count) {
-        idx = a.first + lane;  // first < capacity and count <= capacity
-        if (idx >= a.capacity) idx -= a.capacity;
-        hygt_request* e = ring + idx;
-        fw = ring_load(&e->first_wg);
-        nb = ring_load(&e->nblocks);
-        ex = reinterpret_cast<uint64_t>(ring_load(&e->x));
-        ey = reinterpret_cast<uint64_t>(ring_load(&e->y));
-        ec = reinterpret_cast<uint64_t>(ring_load(&e->cls));
-        et = ring_load(&e->table);
+    const int w = blockIdx.x;
+    int lo = 0, hi = a.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pa->req[mid].first_wg <= w) lo = mid;
+        else hi = mid - 1;
     }
-    const uint64_t below = __ballot(lane < a.count && fw <= w);
-    const int r = __builtin_amdgcn_readfirstlane(__popcll(below) - 1);
-    if (r < 0) return;  // not reached: the first entry's first workgroup is 0
-    const int64_t first_wg = static_cast<int64_t>(read_lane64(static_cast<uint64_t>(fw), r));
-    const int64_t nblocks = static_cast<int64_t>(read_lane64(static_cast<uint64_t>(nb), r));
-    const float* x = global_ptr<const float>(read_lane64(ex, r));
-    float* y = global_ptr<float>(read_lane64(ey, r));
-    const int32_t* cls = global_ptr<const int32_t>(read_lane64(ec, r));
-    int32_t* status = &ring[read_lane64(static_cast<uint64_t>(idx), r)].status;
-    ReqTable tb = pick_table(a, __builtin_amdgcn_readlane(et, r));
-    tb.modes = global_ptr<const int32_t>(reinterpret_cast<uint64_t>(tb.modes));
-    tb.coef = global_ptr<const float>(reinterpret_cast<uint64_t>(tb.coef));
-    tb.signs = global_ptr<const float>(reinterpret_cast<uint64_t>(tb.signs));
-    const int64_t lw = w - first_wg;
+    const int r = lo;
+    const uint64_t ex = reinterpret_cast<uint64_t>(pa->req[r].x);
+    const uint64_t ey = reinterpret_cast<uint64_t>(pa->req[r].y);
+    const uint64_t ec = reinterpret_cast<uint64_t>(pa->req[r].cls);
+    const int64_t nblocks = pa->req[r].nblocks;
+    const int64_t lw = w - pa->req[r].first_wg;
+    int64_t idx = a.first + r;
+    if (idx >= a.capacity) idx -= a.capacity;
+    int32_t* status = a.status + 12 * idx;
+    const int ti = pa->req[r].table;
+    ReqTable tb;
+    tb.modes = global_ptr<const int32_t>(reinterpret_cast<uint64_t>(pa->tab[ti].modes));
+    tb.coef = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->tab[ti].coef));
+    tb.signs = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->tab[ti].signs));
+    tb.log2n = pa->tab[ti].log2n;
+    tb.rounds = pa->tab[ti].rounds;
+    tb.nclasses = pa->tab[ti].nclasses;
+    tb.pad = 0;
+    const float* x = global_ptr<const float>(ex);
+    float* y = global_ptr<float>(ey);
+    const int32_t* cls = ec ? global_ptr<const int32_t>(ec) : nullptr;
     switch (tb.log2n) {
         case 2: request_tile<2, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 3: request_tile<3, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;

@@ -3,13 +3,14 @@
 Requests arrive over time (a codec's frames: each a set of blocks of one
 size, with a class per block). The server keeps, per block size, the
 multiplier tables built once from the angles (hygt_table_build) in device
-memory, and a ring of request descriptors in pinned host memory that the
-device reads itself: submit() writes a request's descriptor into the ring at
-once, and a batch is one launch (hygt_requests_apply) over a run of
-consecutive ring entries, reading each request's blocks from its own input
-tensor and writing its own output tensor. There is no plan, no staging copy
-and no per-batch workspace: a lane of the kernel takes one block and follows
-its own class's table.
+memory, and a ring of request descriptors in pinned host memory: submit()
+writes a request's descriptor into the ring at once, and a batch is one
+launch (hygt_requests_apply) over a run of consecutive ring entries, which
+carries their descriptors as its arguments and reads each request's blocks
+from its own input tensor and writes its own output tensor; the device
+writes each request's status back into its ring entry. There is no plan, no
+staging copy and no per-batch workspace: a lane of the kernel takes one
+block and follows its own class's table.
 
 Batches run in a ring of slots, each with its own stream. Whenever a slot is
 free, the requests at the head of the queue are admitted first come, first
@@ -132,12 +133,31 @@ class Server:
         self.busy_s = 0.0         # summed device time of the finished batches
         self.batch_log = []       # (batch, device start, device end, requests) per finished batch
         self.dispatch_s = 0.0     # host time spent starting batches
-        # device time origin: host time t0 <-> event e0
-        torch.cuda.synchronize(dev)
-        self._e0 = torch.cuda.Event(enable_timing=True)
-        self._e0.record(torch.cuda.current_stream(dev))
-        torch.cuda.synchronize(dev)
-        self._t0 = time.perf_counter()
+        self._e0, self._t0 = self._clock_origin()
+
+    def _clock_origin(self, samples: int = 64):
+        """An event e0 and the host time t0 at which the device recorded it, so
+        that an event's device time maps to host time t0 + elapsed(e0, event).
+        The device records e0 between the host's call and the host seeing it
+        complete; of many tries, the one with the shortest such window gives
+        t0 as its midpoint (off by at most half that window, a few
+        microseconds; taking the host time after a synchronize instead would
+        add its whole latency to every request's measured latency)."""
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.device)
+        best = None
+        for _ in range(samples):
+            ev = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize(self.device)
+            t_before = time.perf_counter()
+            ev.record(stream)
+            while not ev.query():
+                pass
+            t_after = time.perf_counter()
+            if best is None or t_after - t_before < best[2] - best[1]:
+                best = (ev, t_before, t_after)
+        ev, t_before, t_after = best
+        return ev, 0.5 * (t_before + t_after)
 
     def _oldest_live(self) -> int:
         """Ring position of the oldest entry still queued or in flight."""

@@ -319,3 +319,39 @@ def test_requests_apply_rejects_on_the_host():
     # one class: cls may be NULL (checked only; this call does launch, so it
     # is not made here)
     assert ctypes.sizeof(_abi.TableRef) == 24
+
+
+def test_workspace_bytes_at_the_block_limit():
+    """The host layout at HYGT_MAX_BLOCKS: the grouping holds one 4-byte slot
+    per lane of ceil(nblocks / 64) + nclasses tiles of 64, and the size
+    arithmetic neither overflows nor wraps."""
+    ws = _abi.hygt_workspace_bytes
+    top = _abi.HYGT_MAX_BLOCKS
+    assert top == (1 << 31) - 1
+    for nb, d, r, c in [(top, 1, 1, 1), (top, 1, 2, 3), (top - 63, 6, 4, 35), (top, 8, 4, 4096)]:
+        tiles = -(-nb // 64) + c
+        slots = tiles * 64 * 4
+        got = ws(nb, d, r, c)
+        assert got >= slots + tiles * 4, (nb, d, r, c)
+        # the rest (chunk counts and flags, tables) is small next to the slots
+        tables = 2 * c * r * d * (1 << d) * 4 + c * r * d * (1 << d) * 4
+        assert got - slots - tiles * 4 < (64 << 20) + 2 * tables, (nb, d, r, c)
+        assert got % 256 == 0
+    assert ws(top, 1, 1, 1) > ws(top - 64, 1, 1, 1) > ws(top - 128, 1, 1, 1)
+    assert ws(top + 1, 1, 1, 1) == 0
+
+
+def test_ceiling_library_rejects():
+    """The benchmark's memory-ceiling kernels (libhygt_ceiling.so) check their
+    arguments on the host."""
+    import bench
+
+    lib = bench._ceiling_lib()
+    assert lib.hygt_ceiling_stream_copy(FAKE, FAKE * 64, 0, 0) == _abi.HYGT_OK     # nothing
+    assert lib.hygt_ceiling_stream_copy(FAKE, FAKE * 64, 6, 0) == _abi.HYGT_EINVAL  # not float4s
+    assert lib.hygt_ceiling_stream_copy(0, FAKE * 64, 8, 0) == _abi.HYGT_EINVAL
+    assert lib.hygt_ceiling_stream_copy(FAKE, FAKE + 16, 8, 0) == _abi.HYGT_EINVAL  # overlap
+    g = lib.hygt_ceiling_gather_copy
+    assert g(FAKE, FAKE * 64, 100, 7, 4, 35, FAKE, 1 << 30, 0) == _abi.HYGT_EINVAL   # N > 64
+    assert g(FAKE, FAKE * 64, 100, 6, 4, 35, FAKE + 16, 1 << 30, 0) == _abi.HYGT_EWORKSPACE
+    assert g(FAKE, FAKE + 64, 100, 6, 4, 35, FAKE * 64, 1 << 30, 0) == _abi.HYGT_EINVAL  # overlap

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import hygt_oracle as orc
-from paper_2505_21728_amd import synth
+from paper_2505_21728_amd import _abi, synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -154,12 +154,22 @@ def test_mixed_plan_with_empty_segment_and_class_counts():
             plain.append(plan.forward(x).cpu().numpy())
         else:
             plain.append(np.zeros((0, 1 << d), np.float32))
-    mb = hygt.MixedBatch(segs)
+    # a workspace full of stale bytes: the empty segment's part is never
+    # written, and check() must not read it
+    items = [(x.data_ptr(), x.data_ptr(), 0, a.data_ptr(), x.shape[0], d, r, c)
+             for (x, _, a), (d, r, c, _, _) in zip(segs, spec)]
+    wsb = _abi.hygt_mixed_workspace_bytes(_abi.segments(items), len(items))
+    ws = torch.full((wsb,), 0xA5, dtype=torch.uint8, device=dev)
+    mb = hygt.MixedBatch(segs, workspace=ws)
     mb.apply(0)
     torch.cuda.synchronize()
     for i, (y, p) in enumerate(zip(mb.y, plain)):
         assert np.array_equal(y.cpu().numpy(), p), f"segment {i}"
     mb.check()
+    stale = torch.full((hygt.workspace_bytes(0, 6, 4, 7),), 0xA5, dtype=torch.uint8, device=dev)
+    empty = hygt.Plan(segs[1][2], torch.zeros(0, dtype=torch.int32, device=dev), nblocks=0,
+                      workspace=stale)
+    empty.check()
 
 
 def test_mixed_workload_full_size_sampled():

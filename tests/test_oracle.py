@@ -455,6 +455,52 @@ def test_backward_input_gradient_is_the_inverse():
     assert np.allclose(gx, orc.inverse(gy, cls, ang), rtol=0, atol=1e-12)
 
 
+def test_loss_worked_example():
+    """class_log_variance_loss against a value worked out by hand (Sec. V,
+    eq. (10)-(11)): mean (not sum) of squares per class and coefficient,
+    eps inside the log, empty classes skipped."""
+    g = json.load(open(os.path.join(GOLDEN, "class_log_variance_loss_worked.json")))
+    L = orc.class_log_variance_loss(np.array(g["y"], float), np.array(g["cls"]), g["nclasses"],
+                                    eps=g["eps"])
+    assert abs(L - g["loss"]) <= g["tolerance"]
+
+
+def test_loss_at_the_klt_is_the_log_determinant():
+    """For one class with second-moment matrix M = Y^T Y / n, the loss (eps =
+    0) of coefficients in M's eigenbasis (the KLT of Sec. II) is
+    sum log(eigenvalues) = log det M (numpy's slogdet), and any other
+    orthogonal basis gives at least that (Hadamard's inequality): the
+    variance-based rating of Sec. V is smallest at the KLT. Several classes
+    add their own terms."""
+    rng = np.random.default_rng(12)
+    total_klt, total_any, total_det = 0.0, 0.0, 0.0
+    ys, cs = [], []
+    for c in range(3):
+        a = rng.standard_normal((8, 8))
+        y = rng.standard_normal((200, 8)) @ a          # correlated coefficients
+        m = y.T @ y / y.shape[0]
+        _, vecs = np.linalg.eigh(m)
+        sign, logdet = np.linalg.slogdet(m)
+        assert sign > 0
+        klt = y @ vecs
+        one = np.zeros(200, np.int64)
+        l_klt = orc.class_log_variance_loss(klt, one, 1, eps=0.0)
+        l_any = orc.class_log_variance_loss(y, one, 1, eps=0.0)
+        assert abs(l_klt - logdet) < 1e-9
+        assert l_any >= logdet - 1e-9
+        q, _ = np.linalg.qr(rng.standard_normal((8, 8)))
+        assert orc.class_log_variance_loss(y @ q, one, 1, eps=0.0) >= logdet - 1e-9
+        total_klt += l_klt
+        total_det += logdet
+        total_any += l_any
+        ys.append(y)
+        cs.append(np.full(200, c))
+    y = np.concatenate(ys)
+    cls = np.concatenate(cs)
+    assert abs(orc.class_log_variance_loss(y, cls, 3, eps=0.0) - total_any) < 1e-9
+    assert total_klt == pytest.approx(total_det, abs=1e-8)
+
+
 def test_loss_gradient_and_empty_classes():
     rng = np.random.default_rng(5)
     y = rng.standard_normal((9, 4))
@@ -625,6 +671,29 @@ def pin_int_error_bound_and_bias(o):
     # the inverse undoes the forward up to the same kind of rounding error
     back = o.inverse_int(y, cls, codes)
     assert np.all(np.linalg.norm(back - x, axis=1) <= 2 * bound)
+
+
+def test_int_error_bound_worked_and_attained():
+    """int_error_bound() against values worked out by hand, and not vacuous:
+    for one butterfly (N = 2, one pass) some integer input on [-255, 255]^2
+    comes within 5% of the bound for each of several codes, i.e. the
+    per-pass term is nearly attained; longer chains add these terms by the
+    triangle inequality."""
+    g = json.load(open(os.path.join(GOLDEN, "int_error_bound_worked.json")))
+    for case in g["cases"]:
+        b = orc.int_error_bound(case["x_norm"], case["n_elems"], case["passes"])
+        assert abs(b - case["bound"]) <= g["tolerance"], case
+    grid = np.arange(-255, 256)
+    x = np.array(np.meshgrid(grid, grid)).reshape(2, -1).T
+    norms = np.linalg.norm(x.astype(np.float64), axis=1)
+    bound = np.array([orc.int_error_bound(v, 2, 1) for v in norms])
+    for code in (37, 100, 160, 201):
+        codes = np.array([[[[code]]]], dtype=np.uint8)
+        y = orc.forward_int(x, None, codes)
+        ref = orc.forward(x.astype(np.float64), None, orc.angles_from_codes(codes))
+        ratio = np.linalg.norm(y - ref, axis=1) / bound
+        assert ratio.max() <= 1.0
+        assert ratio.max() >= 0.95, code
 
 
 def test_int_multiplier_table():
