@@ -46,10 +46,18 @@ constexpr int kAngleBatch = 2048;
 // Angles each thread of a table builder loads at once.
 constexpr int kLoadsPerThread = 8;
 
+// Passes of one batch of a table builder, at most (R <= 64 and d <= 8 give at
+// most 512 passes; N <= 64 keeps one mask word per pass, N > 64 four, with at
+// most 32 passes per batch).
+constexpr int kMaskWords = 512;
+
 // LDS of a table builder.
 struct TableShared {
     float tanh_phi[kAngleBatch];    // tan(phi/2) of the batch's angles (cos for bits >= 6)
     float sin_phi[kAngleBatch];     // sin(phi) (sin theta for bits >= 6)
+    uint64_t emask[kMaskWords];     // elements negated by each pass of the batch
+    uint64_t smask[kMaskWords];     // stored signs before each pass of the batch
+    uint64_t send[4];               // stored signs after the batch
     signed char flip[kAngleBatch];  // -1 where |theta| > pi/2
 };
 
@@ -69,6 +77,43 @@ struct SignBits {
         return static_cast<int>((word >> (i & 63)) & 1u);
     }
 };
+
+// 1 / n!, exact to rounding (n! itself is exact in FP64 for n <= 18).
+constexpr double inv_factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
+}
+
+// sin h and cos h for |h| <= pi/4, in FP64, from their Taylor series
+// sin h = h + h z (-1/3! + z/5! - ... - z^8/19!) and
+// cos h = 1 + z (-1/2! + z/4! - ... - z^8/18!), z = h^2, by Horner's rule in
+// z (the first dropped terms, h^21/21! and h^20/20!, are below 1e-20 on this
+// range). The library's double sincos reduces arguments of any size and took
+// about 1 us per angle and wavefront here; these angles never exceed pi/4.
+__device__ __forceinline__ void sincos_quarter(double h, double* s, double* c) {
+    const double z = h * h;
+    double ps = -inv_factorial(19);
+    double pc = -inv_factorial(18);
+    ps = fma(z, ps, inv_factorial(17));
+    pc = fma(z, pc, inv_factorial(16));
+    ps = fma(z, ps, -inv_factorial(15));
+    pc = fma(z, pc, -inv_factorial(14));
+    ps = fma(z, ps, inv_factorial(13));
+    pc = fma(z, pc, inv_factorial(12));
+    ps = fma(z, ps, -inv_factorial(11));
+    pc = fma(z, pc, -inv_factorial(10));
+    ps = fma(z, ps, inv_factorial(9));
+    pc = fma(z, pc, inv_factorial(8));
+    ps = fma(z, ps, -inv_factorial(7));
+    pc = fma(z, pc, -inv_factorial(6));
+    ps = fma(z, ps, inv_factorial(5));
+    pc = fma(z, pc, inv_factorial(4));
+    ps = fma(z, ps, -inv_factorial(3));
+    pc = fma(z, pc, -inv_factorial(2));
+    *s = fma(h * z, ps, h);
+    *c = fma(z, pc, 1.0);
+}
 
 // Angle of 8-bit parameter code q (Fig. 6 keeps one byte per parameter and
 // a shared table of multipliers): q steps of 2 pi / 256 from -pi, so that
@@ -144,119 +189,134 @@ __device__ __forceinline__ void build_table(TableShared& sh, int dir, int c,
                 const int kk = p % log2n;
                 const int k = dir ? log2n - 1 - kk : kk;
                 const double t = dir ? -th[u] : th[u];
-                double sn, cs;
-                if (k >= kLaneBits) {  // (cos, sin) form, no reduction
-                    sincos(t, &sn, &cs);
-                    sh.tanh_phi[e] = static_cast<float>(cs);
-                    sh.sin_phi[e] = static_cast<float>(sn);
-                    sh.flip[e] = 1;
-                    continue;
-                }
                 // G(t) = f * G(phi) with |phi| <= pi/2
                 const double pi = 3.141592653589793238462643383279502884;
                 double phi = t;
                 signed char f = 1;
                 if (phi > pi / 2) { phi -= pi; f = -1; }
                 else if (phi < -pi / 2) { phi += pi; f = -1; }
-                // tan(phi / 2) = sin(phi) / (1 + cos(phi)), with 1 + cos(phi) >= 1
-                sincos(phi, &sn, &cs);
-                sh.tanh_phi[e] = static_cast<float>(sn / (1.0 + cs));
+                double sh2, ch2;
+                sincos_quarter(0.5 * phi, &sh2, &ch2);
+                const double sn = 2.0 * sh2 * ch2;           // sin(phi)
+                if (k >= kLaneBits) {  // (cos, sin) form of t itself: no reduction
+                    const double cs = (ch2 - sh2) * (ch2 + sh2);  // cos(phi)
+                    sh.tanh_phi[e] = static_cast<float>(f * cs);
+                    sh.sin_phi[e] = static_cast<float>(f * sn);
+                    sh.flip[e] = 1;
+                    continue;
+                }
+                sh.tanh_phi[e] = static_cast<float>(sh2 / ch2);  // tan(phi / 2)
                 sh.sin_phi[e] = static_cast<float>(sn);
                 sh.flip[e] = f;
             }
         }
         __syncthreads();
-        // The sign walk is sequential over the passes: one wavefront takes
-        // it, with the stored signs of all elements as bit masks held by
-        // every lane. A pair (m, n) rotated with flip f = -1 (G(theta) =
-        // -G(phi)) negates both of its stored values, and a pair whose two
-        // stored signs differ is rotated by -phi; a lane per pair (two for
-        // N = 256) writes the multipliers, and ballots gather the new masks.
-        if (tid < 64 && n <= 64) {
-            // one sign word, lane j = pair j; no cross-wavefront passes
-            const int lane = tid;
-            const bool own = lane < half;
-            uint64_t S0 = S.w0;
-            for (int p = p0; p < p1; ++p) {
-                const int kk = p % log2n;
-                const int k = dir ? log2n - 1 - kk : kk;
-                const int e = (p - p0) * half + (own ? lane : 0);
-                const int f = sh.flip[e];
-                const float tp = sh.tanh_phi[e];
-                const float sp = sh.sin_phi[e];
-                const uint64_t F = __ballot(own && f < 0);
-                const int m = insert_zero_bit(lane, k) & 63;
-                const int nn = (m + (1 << k)) & 63;
-                const bool differ = own && (((S0 >> m) ^ (S0 >> nn)) & 1u);
-                // a pair whose stored signs differ is rotated by -phi
-                const float g = differ ? -1.0f : 1.0f;
-                if (own) {
-                    float* cp = cbase + static_cast<size_t>(p) * n;
-                    *reinterpret_cast<float2*>(cp + 2 * lane) = make_float2(g * tp, -g * sp);
-                }
-                if (pair_flip != nullptr) {
-                    const uint64_t bits = __ballot(differ);
-                    if (lane == 0) pair_flip[p] = static_cast<uint32_t>(bits);
-                }
-                // element l takes the flip of its pair, l with bit k removed
-                const int jl = ((lane >> (k + 1)) << k) | (lane & ((1 << k) - 1));
-                S0 ^= __ballot(lane < n && ((F >> jl) & 1u));
+        // Signs. Stored signs change only where a pair is rotated with flip
+        // f = -1 (G(theta) = -G(phi)), which negates both of its values, and
+        // which pairs those are depends on the angles alone. So the masks of
+        // elements negated by each pass (E_p) are found for all passes in
+        // parallel, the stored signs before each pass (S_p, the running XOR
+        // of the E's) follow in one short sequential sweep, and the
+        // multipliers of all passes are again written in parallel: a pair
+        // whose two stored signs differ is rotated by -phi. A wavefront takes
+        // every fourth pass; a lane takes pair j (and j + 64 for N = 256),
+        // the masks held as bit masks over the elements.
+        const int wave = tid >> 6;
+        const int lane = tid & 63;
+        const int nwaves = static_cast<int>(blockDim.x) >> 6;
+        constexpr int NW = 4;  // mask words per pass (256 elements)
+        const int words = n > 64 ? NW : 1;
+        // E_p of the batch's passes
+        for (int p = p0 + wave; p < p1; p += nwaves) {
+            const int kk = p % log2n;
+            const int k = dir ? log2n - 1 - kk : kk;
+            const int base = (p - p0) * half;
+            if (k >= kLaneBits) {  // (cos, sin) form: no flips
+                if (lane < words) sh.emask[(p - p0) * words + lane] = 0;
+                continue;
             }
-            S.w0 = S0;
-        } else if (tid < 64) {
-            // N = 128, 256: up to four sign words and two pairs per lane (j
-            // and j + 64), all in named registers (no arrays indexed at run
-            // time, which would go to scratch memory)
-            const int lane = tid;
-            for (int p = p0; p < p1; ++p) {
-                const int kk = p % log2n;
-                const int k = dir ? log2n - 1 - kk : kk;
-                float* cp = cbase + static_cast<size_t>(p) * n;
-                const int j0 = lane, j1 = lane + 64;
-                const bool own1 = j1 < half;
-                const int e0 = (p - p0) * half + j0;
-                const int e1 = (p - p0) * half + (own1 ? j1 : j0);
-                const int f0 = sh.flip[e0], f1 = sh.flip[e1];
-                const float tp0 = sh.tanh_phi[e0], tp1 = sh.tanh_phi[e1];
-                const float sp0 = sh.sin_phi[e0], sp1 = sh.sin_phi[e1];
-                const uint64_t F0 = __ballot(f0 < 0);
-                const uint64_t F1 = __ballot(own1 && f1 < 0);
-                // a pair whose stored signs differ is rotated by -phi; in the
-                // (cos, sin) form (k >= 6) the sine is multiplied by sm * sq
-                // and the signs stay
-                auto multipliers = [&](int j, float tp, float sp) {
-                    const int m = insert_zero_bit(j, k);
-                    const int nn = m + (1 << k);
-                    const float g = S.bit(m) != S.bit(nn) ? -1.0f : 1.0f;
-                    *reinterpret_cast<float2*>(cp + 2 * j) =
-                        k >= kLaneBits ? make_float2(tp, g * sp) : make_float2(g * tp, -g * sp);
-                };
-                multipliers(j0, tp0, sp0);
-                if (own1) multipliers(j1, tp1, sp1);
-                if (k < kLaneBits) {
-                    // element l takes the flip of its pair, l with bit k removed
-                    auto flipped = [&](int l) {
-                        const int j = ((l >> (k + 1)) << k) | (l & ((1 << k) - 1));
-                        const uint64_t fw = (j >> 6) ? F1 : F0;
-                        return l < n && ((fw >> (j & 63)) & 1u);
-                    };
-                    const uint64_t E0 = __ballot(flipped(lane));
-                    const uint64_t E1 = __ballot(flipped(lane + 64));
-                    const uint64_t E2 = __ballot(flipped(lane + 128));
-                    const uint64_t E3 = __ballot(flipped(lane + 192));
-                    S.w0 ^= E0;
-                    S.w1 ^= E1;
-                    S.w2 ^= E2;
-                    S.w3 ^= E3;
+            // F: the pairs rotated with flip -1, a bit per pair (two words for N = 256)
+            const bool own0 = lane < half;
+            const bool own1 = lane + 64 < half;
+            const uint64_t F0 = __ballot(own0 && sh.flip[base + (own0 ? lane : 0)] < 0);
+            const uint64_t F1 = __ballot(own1 && sh.flip[base + (own1 ? lane + 64 : 0)] < 0);
+            // element l takes the flip of its pair, l with bit k removed
+            auto flipped = [&](int l) {
+                const int j = ((l >> (k + 1)) << k) | (l & ((1 << k) - 1));
+                const uint64_t fw = (j >> 6) ? F1 : F0;
+                return l < n && ((fw >> (j & 63)) & 1u);
+            };
+            const uint64_t E0 = __ballot(flipped(lane));
+            if (words == 1) {
+                if (lane == 0) sh.emask[p - p0] = E0;
+            } else {
+                const uint64_t E1 = __ballot(flipped(lane + 64));
+                const uint64_t E2 = __ballot(flipped(lane + 128));
+                const uint64_t E3 = __ballot(flipped(lane + 192));
+                if (lane == 0) {
+                    uint64_t* e = sh.emask + (p - p0) * NW;
+                    e[0] = E0;
+                    e[1] = E1;
+                    e[2] = E2;
+                    e[3] = E3;
                 }
             }
         }
+        __syncthreads();
+        // S_p for the batch's passes: lane w of wavefront 0 sweeps word w
+        if (tid < words) {
+            uint64_t sw = tid == 0 ? S.w0 : tid == 1 ? S.w1 : tid == 2 ? S.w2 : S.w3;
+            for (int q = 0; q < p1 - p0; ++q) {
+                sh.smask[q * words + tid] = sw;
+                sw ^= sh.emask[q * words + tid];
+            }
+            sh.send[tid] = sw;
+        }
+        __syncthreads();
+        // multipliers of the batch's passes
+        for (int p = p0 + wave; p < p1; p += nwaves) {
+            const int kk = p % log2n;
+            const int k = dir ? log2n - 1 - kk : kk;
+            const int base = (p - p0) * half;
+            SignBits Sp = {sh.smask[(p - p0) * words], 0, 0, 0};
+            if (words > 1) {
+                Sp.w1 = sh.smask[(p - p0) * words + 1];
+                Sp.w2 = sh.smask[(p - p0) * words + 2];
+                Sp.w3 = sh.smask[(p - p0) * words + 3];
+            }
+            float* cp = cbase + static_cast<size_t>(p) * n;
+            uint64_t differ_bits = 0;
+            auto multipliers = [&](int j) {
+                const int m = insert_zero_bit(j, k);
+                const int nn = m + (1 << k);
+                const bool differ = Sp.bit(m) != Sp.bit(nn);
+                const float g = differ ? -1.0f : 1.0f;
+                const float tp = sh.tanh_phi[base + j];
+                const float sp = sh.sin_phi[base + j];
+                // (cos, sin) form (k >= 6): the sine times the pair's signs,
+                // which the pass leaves unchanged
+                *reinterpret_cast<float2*>(cp + 2 * j) =
+                    k >= kLaneBits ? make_float2(tp, g * sp) : make_float2(g * tp, -g * sp);
+                return differ;
+            };
+            const bool d0 = lane < half && multipliers(lane);
+            if (lane + 64 < half) multipliers(lane + 64);
+            differ_bits = __ballot(d0);
+            if (pair_flip != nullptr && lane == 0) pair_flip[p] = static_cast<uint32_t>(differ_bits);
+        }
+        // the signs after the batch (read by every thread), and the LDS of
+        // this batch free for the next
+        __syncthreads();
+        S.w0 = sh.send[0];
+        if (words > 1) {
+            S.w1 = sh.send[1];
+            S.w2 = sh.send[2];
+            S.w3 = sh.send[3];
+        }
     }
-    // The final signs; the masks are the same in every lane of wavefront 0.
-    if (tid < 64) {
-        for (int i = tid; i < n; i += 64) sbase[i] = S.bit(i) ? -1.0f : 1.0f;
-        if (tid == 0) *mode = (S.w0 | S.w1 | S.w2 | S.w3) != 0 ? 1 : 0;
-    }
+    // The final signs (the same masks in every thread).
+    for (int i = tid; i < n; i += blockDim.x) sbase[i] = S.bit(i) ? -1.0f : 1.0f;
+    if (tid == 0) *mode = (S.w0 | S.w1 | S.w2 | S.w3) != 0 ? 1 : 0;
 }
 
 }  // namespace table
