@@ -512,10 +512,17 @@ def main():
     run_steps(max(args.warmup, 1))
     _abi._check(_abi.hygt_check_error(wp, wsb, handle), "hygt_check_error")
     torch.cuda.synchronize()
+    d0 = torch.cuda.Event(enable_timing=True)
+    d1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    d0.record(main)
     run_steps(args.steps)
+    d1.record(main)
     torch.cuda.synchronize()
     ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    # the same steps timed on the device (from the first launch to the last),
+    # which leaves out the host's start-up latency; a diagnostic, not `value`
+    device_ms_per_step = d0.elapsed_time(d1) / args.steps
     value = NBLOCKS / (ms_per_step / 1e3)
 
     # Kernel rooflines: the forward (and inverse) launches alone, back to back
@@ -567,6 +574,7 @@ def main():
                                "AR(1) rho=0.9 sigma=40 int-valued FP32",
                    "nblocks": NBLOCKS, "N": N, "rounds": ROUNDS, "classes": NCLASSES,
                    "input_ring": RING},
+        "device_ms_per_step": device_ms_per_step,
         "step_hbm_gbps": step_gbps,
         "step_pct_peak": 100.0 * step_gbps / HBM_PEAK_GBPS,
         "fwd_ms": fwd_ms,

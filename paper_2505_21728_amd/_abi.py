@@ -161,70 +161,6 @@ def _check(status: int, where: str) -> None:
         raise HygtError(status, where)
 
 
-def hygt_workspace_bytes(nblocks: int, log2n: int, rounds: int, nclasses: int) -> int:
-    return int(load().hygt_workspace_bytes(nblocks, log2n, rounds, nclasses))
-
-
-def hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr, ws_bytes,
-              stream) -> int:
-    return load().hygt_plan(cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
-                            ws_bytes, stream)
-
-
-def hygt_plan_int(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr, ws_bytes,
-                  stream) -> int:
-    return load().hygt_plan_int(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr,
-                                ws_bytes, stream)
-
-
-def hygt_apply_int(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr, ws_bytes,
-                   stream) -> int:
-    return load().hygt_apply_int(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction,
-                                 ws_ptr, ws_bytes, stream)
-
-
-def hygt_apply_perm(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, perm_ptr, ws_ptr,
-                    ws_bytes, stream) -> int:
-    return load().hygt_apply_perm(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction,
-                                  perm_ptr, ws_ptr, ws_bytes, stream)
-
-
-def hygt_plan_codes(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr, ws_bytes,
-                    stream) -> int:
-    return load().hygt_plan_codes(cls_ptr, nblocks, log2n, rounds, codes_ptr, nclasses, ws_ptr,
-                                  ws_bytes, stream)
-
-
-def hygt_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr, ws_bytes,
-               stream) -> int:
-    return load().hygt_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, direction, ws_ptr,
-                             ws_bytes, stream)
-
-
-def hygt_forward(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
-                 ws_bytes, stream) -> int:
-    return load().hygt_forward(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr,
-                               nclasses, ws_ptr, ws_bytes, stream)
-
-
-def hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses, ws_ptr,
-                 ws_bytes, stream) -> int:
-    return load().hygt_inverse(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr,
-                               nclasses, ws_ptr, ws_bytes, stream)
-
-
-def hygt_backward(y_ptr, gy_ptr, gx_ptr, ga_ptr, nblocks, log2n, rounds, angles_ptr, nclasses,
-                  ws_ptr, ws_bytes, stream) -> int:
-    return load().hygt_backward(y_ptr, gy_ptr, gx_ptr, ga_ptr, nblocks, log2n, rounds, angles_ptr,
-                                nclasses, ws_ptr, ws_bytes, stream)
-
-
-def hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr, ws_ptr, ws_bytes,
-                     stream) -> int:
-    return load().hygt_dense_apply(x_ptr, y_ptr, nblocks, log2n, rounds, nclasses, mats_ptr,
-                                   ws_ptr, ws_bytes, stream)
-
-
 def segments(items) -> "ctypes.Array[Segment]":
     """A ctypes array of hygt_segment from (x, y, cls, angles, nblocks, log2n,
     rounds, nclasses) tuples of integers (pointers as ints)."""
@@ -232,22 +168,6 @@ def segments(items) -> "ctypes.Array[Segment]":
     for i, (x, y, cls, ang, nb, d, r, c) in enumerate(items):
         arr[i] = Segment(x, y, cls, ang, nb, d, r, c, 0)
     return arr
-
-
-def hygt_mixed_workspace_bytes(segs, nseg) -> int:
-    return int(load().hygt_mixed_workspace_bytes(segs, nseg))
-
-
-def hygt_mixed_plan(segs, nseg, ws_ptr, ws_bytes, stream) -> int:
-    return load().hygt_mixed_plan(segs, nseg, ws_ptr, ws_bytes, stream)
-
-
-def hygt_mixed_num_configs() -> int:
-    return load().hygt_mixed_num_configs()
-
-
-def hygt_mixed_apply(segs, nseg, direction, config, ws_ptr, ws_bytes, stream) -> int:
-    return load().hygt_mixed_apply(segs, nseg, direction, config, ws_ptr, ws_bytes, stream)
 
 
 def hygt_mixed_autotune(segs, nseg, direction, ws_ptr, ws_bytes, stream):
@@ -265,33 +185,6 @@ def hygt_mixed_graph_create(segs, nseg, direction, config, ws_ptr, ws_bytes, str
     return st, handle.value
 
 
-def hygt_graph_launch(handle, stream) -> int:
-    return load().hygt_graph_launch(handle, stream)
-
-
-def hygt_graph_destroy(handle) -> int:
-    return load().hygt_graph_destroy(handle)
-
-
-def hygt_check_error(ws_ptr, ws_bytes, stream) -> int:
-    return load().hygt_check_error(ws_ptr, ws_bytes, stream)
-
-
-def hygt_transform_noalloc(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds, angles_ptr, nclasses,
-                           direction, stream) -> int:
-    return load().hygt_transform_noalloc(x_ptr, y_ptr, cls_ptr, nblocks, log2n, rounds,
-                                         angles_ptr, nclasses, direction, stream)
-
-
-def hygt_table_bytes(log2n, rounds, nclasses) -> int:
-    return int(load().hygt_table_bytes(log2n, rounds, nclasses))
-
-
-def hygt_table_build(angles_ptr, log2n, rounds, nclasses, table_ptr, table_bytes, stream) -> int:
-    return load().hygt_table_build(angles_ptr, log2n, rounds, nclasses, table_ptr, table_bytes,
-                                   stream)
-
-
 def table_refs(items) -> "ctypes.Array[TableRef]":
     """A ctypes array of hygt_table_ref from (table, log2n, rounds, nclasses)
     tuples (pointers as ints)."""
@@ -301,7 +194,17 @@ def table_refs(items) -> "ctypes.Array[TableRef]":
     return arr
 
 
-def hygt_requests_apply(ring_ptr, capacity, first, count, tables, ntables, direction,
-                        stream) -> int:
-    return load().hygt_requests_apply(ring_ptr, capacity, first, count, tables, ntables,
-                                      direction, stream)
+def _delegate(name):
+    def call(*args):
+        return getattr(load(), name)(*args)
+
+    call.__name__ = call.__qualname__ = name
+    call.__doc__ = f"{name}() of include/hygt.h, arguments in the order declared there."
+    return call
+
+
+# Every other entry point is a plain call with the arguments of the header.
+for _name in _SIGNATURES:
+    if _name not in globals():
+        globals()[_name] = _delegate(_name)
+del _name
