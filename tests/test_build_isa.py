@@ -9,6 +9,11 @@ its gfx950 code object, which is disassembled and its kernel metadata read.
   compiler from pairing ordinary float operations into them.
 - No kernel uses scratch memory (private segment): register spills or
   arrays indexed at run time would put per-lane data in slow memory.
+- The tile load of 8x8 blocks (load_tile in hygt_tile.h) waits for its LDS
+  DMA with a hand-counted "s_waitcnt vmcnt(8)": all but the 8 youngest
+  vector memory operations. That is right only if at least 8 of them were
+  issued after the last DMA instruction; every such wait in the built code
+  is checked for it.
 """
 
 import os
@@ -87,3 +92,34 @@ def test_no_kernel_uses_scratch(code_objects):
         assert len(names) == len(sizes)  # a unit may hold no kernel (device data only)
         using = [n for n, s in zip(names, sizes) if int(s) != 0]
         assert not using, f"kernels with scratch memory: {using}"
+
+
+_VMEM = re.compile(r"^\s+(global_|buffer_|flat_|scratch_)\w+", re.M)
+
+
+def test_dma_wait_counts(code_objects):
+    objdump = _tool("llvm-objdump")
+    waits = 0
+    for co in code_objects:
+        text = subprocess.run([objdump, "-d", str(co)], check=True, capture_output=True,
+                              text=True).stdout
+        lines = text.splitlines()
+        for i, line in enumerate(lines):
+            if "s_waitcnt vmcnt(8)" not in line:
+                continue
+            # back to the DMA instruction before this wait, counting the
+            # vector memory operations issued in between
+            after_dma = 0
+            for prev in reversed(lines[:i]):
+                if "global_load_lds_dwordx4" in prev:
+                    break
+                if prev.strip().endswith(":") or "s_endpgm" in prev:
+                    after_dma = None        # another block: not a tile load's wait
+                    break
+                if _VMEM.match(prev):
+                    after_dma += 1
+            if after_dma is None:
+                continue
+            waits += 1
+            assert after_dma >= 8, f"{co.name}: only {after_dma} operations after the DMA"
+    assert waits > 0   # the tile loads of N = 64 were found
