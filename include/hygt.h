@@ -295,6 +295,17 @@ size_t hygt_mixed_workspace_bytes(const hygt_segment* segs, int nseg);
 int hygt_mixed_plan(const hygt_segment* segs, int nseg, void* workspace, size_t workspace_bytes,
                     hipStream_t stream);
 
+/* hygt_mixed_plan() without the multiplier tables: only the class grouping
+ * of every segment, for callers whose angles have not changed since the
+ * last hygt_mixed_plan() on this workspace with these segments' sizes (the
+ * classes, the block counts and the buffers may change). The tables of that
+ * plan stay in the workspace and are used as they are; with other angles, or
+ * on a workspace that never held such a plan, the transform uses whatever
+ * the workspace holds. A training step that changes the angles plans again
+ * with hygt_mixed_plan(). */
+int hygt_mixed_regroup(const hygt_segment* segs, int nseg, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream);
+
 /* Number of launch configurations of hygt_mixed_apply(). */
 int hygt_mixed_num_configs(void);
 

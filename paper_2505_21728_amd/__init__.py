@@ -351,13 +351,17 @@ class MixedBatch:
     def _s(self, stream):
         return _stream_handle(stream if stream is not None else self._stream)
 
-    def plan(self, stream=None):
-        """Plans every segment (classes and angles as the buffers hold them now)."""
+    def plan(self, stream=None, tables: bool = True):
+        """Plans every segment (classes and angles as the buffers hold them
+        now). tables=False only regroups the blocks by class and keeps the
+        multiplier tables of the last full plan, for angles that have not
+        changed since (hygt_mixed_regroup)."""
         torch = _torch()
+        fn = _abi.hygt_mixed_plan if tables else _abi.hygt_mixed_regroup
         with torch.cuda.device(self.device):
-            st = _abi.hygt_mixed_plan(self._segs, self._n, self.workspace.data_ptr(),
-                                      self.ws_bytes, self._s(stream))
-        _abi._check(st, "hygt_mixed_plan")
+            st = fn(self._segs, self._n, self.workspace.data_ptr(), self.ws_bytes,
+                    self._s(stream))
+        _abi._check(st, "hygt_mixed_plan" if tables else "hygt_mixed_regroup")
 
     def apply(self, direction=HYGT_FORWARD, config=None, stream=None):
         """One launch over all segments; returns the output tensors."""

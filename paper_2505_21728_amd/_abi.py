@@ -93,6 +93,7 @@ _SIGNATURES = {
                                     _c.c_void_p]),
     "hygt_mixed_workspace_bytes": (_c.c_size_t, [_SEGS, _c.c_int]),
     "hygt_mixed_plan": (_c.c_int, [_SEGS, _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "hygt_mixed_regroup": (_c.c_int, [_SEGS, _c.c_int, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "hygt_mixed_num_configs": (_c.c_int, []),
     "hygt_mixed_apply": (_c.c_int, [_SEGS, _c.c_int, _c.c_int, _c.c_int, _c.c_void_p,
                                     _c.c_size_t, _c.c_void_p]),

@@ -234,13 +234,14 @@ int mixed_args(const hygt_segment* segs, int nseg, const void* ws, size_t ws_byt
 }
 
 int mixed_plan_impl(const hygt_segment* segs, int nseg, void* ws, size_t ws_bytes,
-                    hipStream_t stream) {
+                    hipStream_t stream, bool tables = true) {
     if (int s = check_segments(segs, nseg)) return s;
     size_t offsets[HYGT_MAX_SEGMENTS];
     const size_t total = mixed_layout(segs, nseg, offsets);
     if (ws == nullptr || ws_bytes < total || !aligned(ws, 256)) return HYGT_EWORKSPACE;
     // Every segment with blocks gets its share of the same two launches.
     hygt::PlanArgs a{};
+    a.tables = tables ? 1 : 0;
     int64_t count_wgs = 0, place_wgs = 0;
     for (int i = 0; i < nseg; ++i) {
         const hygt_segment& g = segs[i];
@@ -270,7 +271,7 @@ int mixed_plan_impl(const hygt_segment* segs, int nseg, void* ws, size_t ws_byte
         m.rounds = g.rounds;
         m.nclasses = g.nclasses;
         count_wgs += l.nchunks;
-        place_wgs += 2 * static_cast<int64_t>(g.nclasses) + l.nchunks;
+        place_wgs += (tables ? 2 * static_cast<int64_t>(g.nclasses) : 0) + l.nchunks;
     }
     const hipError_t e = hygt::launch_plan_mixed(a, count_wgs, place_wgs, stream);
     return e == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
@@ -404,6 +405,11 @@ size_t hygt_mixed_workspace_bytes(const hygt_segment* segs, int nseg) {
 int hygt_mixed_plan(const hygt_segment* segs, int nseg, void* workspace, size_t workspace_bytes,
                     hipStream_t stream) {
     return mixed_plan_impl(segs, nseg, workspace, workspace_bytes, stream);
+}
+
+int hygt_mixed_regroup(const hygt_segment* segs, int nseg, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+    return mixed_plan_impl(segs, nseg, workspace, workspace_bytes, stream, false);
 }
 
 int hygt_mixed_num_configs(void) { return hygt::kMixedConfigs; }

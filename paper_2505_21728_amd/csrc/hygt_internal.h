@@ -168,7 +168,7 @@ struct PlanSeg {
     int64_t chunk;
     int64_t max_tiles;
     int64_t count_begin;  // first workgroup of launch A (counting)
-    int64_t place_begin;  // first workgroup of launch B (tables, then placing)
+    int64_t place_begin;  // first workgroup of launch B (tables if built, then placing)
     int64_t interleave;   // WsLayout::interleave
     int log2n;
     int rounds;
@@ -179,7 +179,7 @@ struct PlanSeg {
 struct PlanArgs {
     PlanSeg seg[kMaxSegments];
     int nseg;
-    int pad;
+    int tables;  // 1: the placing launch also builds every segment's multiplier tables
 };
 
 // The plans of every segment with blocks in two launches of count_wgs and

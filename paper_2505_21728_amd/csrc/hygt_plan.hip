@@ -560,12 +560,13 @@ __global__ __launch_bounds__(kPlanThreads) void plan_place_mixed_kernel(PlanArgs
     const int64_t w = blockIdx.x;
     const PlanSeg& g = a.seg[plan_segment(a, w, true)];
     const int64_t local = w - g.place_begin;
-    if (local < 2 * g.nclasses) {
+    const int64_t ntab = a.tables ? 2 * static_cast<int64_t>(g.nclasses) : 0;
+    if (local < ntab) {
         build_tables_wg(place_dyn, static_cast<int>(local), g.angles, nullptr, g.log2n, g.rounds,
                         0, g.nclasses, g.modes, g.coef, g.signs);
         return;
     }
-    place_chunk(place_dyn, local - 2 * static_cast<int64_t>(g.nclasses), g.cls, g.nblocks,
+    place_chunk(place_dyn, local - ntab, g.cls, g.nblocks,
                 g.nclasses, g.nchunks, g.chunk, g.max_tiles, g.interleave, g.counts,
                 g.tile_class, g.perm);
 }

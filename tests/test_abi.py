@@ -217,6 +217,9 @@ def test_mixed_sizes_and_rejects():
     assert _abi.hygt_mixed_workspace_bytes(bad, 1) == 0
     assert _abi.hygt_mixed_plan(bad, 1, FAKE, 1 << 30, 0) == _abi.HYGT_EINVAL
     assert _abi.hygt_mixed_plan(segs, 3, FAKE, total - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert _abi.hygt_mixed_regroup(bad, 1, FAKE, 1 << 30, 0) == _abi.HYGT_EINVAL
+    assert _abi.hygt_mixed_regroup(segs, 3, FAKE, total - 1, 0) == _abi.HYGT_EWORKSPACE
+    assert _abi.hygt_mixed_regroup(segs, 0, FAKE, total, 0) == _abi.HYGT_EINVAL
     n = _abi.hygt_mixed_num_configs()
     assert n >= 2
     a = _abi.hygt_mixed_apply

@@ -223,3 +223,31 @@ def test_mixed_plan_many_classes():
     for i, (y, p) in enumerate(zip(mb.y, plain)):
         assert np.array_equal(y.cpu().numpy(), p), f"segment {i}"
     mb.check()
+
+
+def test_regroup_keeps_tables_and_matches_a_full_plan():
+    """hygt_mixed_regroup after new classes (same angles, same sizes) gives,
+    bit for bit, what a full hygt_mixed_plan of the new classes gives."""
+    dev = _dev()
+    import paper_2505_21728_amd as hygt
+    spec = [(4, 2, 35, 5000), (6, 4, 35, 3000), (8, 4, 35, 700)]
+    segs, fresh = [], []
+    for i, (d, r, c, nb) in enumerate(spec):
+        _say(f"[gpu] regroup: segment {i} d={d} B={nb}")
+        ang = _to(synth.angles(c, r, d, seed=80 + i), dev)
+        x = _to(synth.gaussian_blocks(nb, 1 << d, seed=81 + i), dev)
+        cls = _to(synth.classes(nb, c, seed=82 + i), dev)
+        segs.append((x, cls, ang))
+    mb = hygt.MixedBatch(segs)
+    mb.plan()
+    mb.apply(0)
+    for i, (d, r, c, nb) in enumerate(spec):                # new classes, same buffers
+        mb.cls[i].copy_(_to(synth.classes(nb, c, seed=90 + i), dev))
+    mb.plan(tables=False)
+    got = [y.clone() for y in mb.apply(0)]
+    mb.plan()
+    want = mb.apply(0)
+    torch.cuda.synchronize()
+    for i, (g, w) in enumerate(zip(got, want)):
+        assert torch.equal(g, w), f"segment {i}"
+    mb.check()
