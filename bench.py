@@ -65,8 +65,8 @@ FLOPS_PER_BLOCK = 6 * ROUNDS * LOG2N * (N // 2)
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=1 << 16,
                     help="blocks of the batch run through the oracle on the host (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -494,34 +494,50 @@ def main():
     yt = torch.empty_like(xs[0])
     zt = torch.empty_like(xs[0])
     wsb = hygt.workspace_bytes(NBLOCKS, LOG2N, ROUNDS, NCLASSES)
-    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    wss = [torch.empty(wsb, dtype=torch.uint8, device=dev) for _ in range(2)]
     main = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
     from paper_2505_21728_amd import _abi
 
-    handle = main.cuda_stream
+    side = torch.cuda.Stream(device=dev)
     xp = [t.data_ptr() for t in xs]
     cp = [t.data_ptr() for t in cs]
-    ap, yp, zp, wp = at.data_ptr(), yt.data_ptr(), zt.data_ptr(), ws.data_ptr()
+    ap, yp, zp = at.data_ptr(), yt.data_ptr(), zt.data_ptr()
+    wp = [w.data_ptr() for w in wss]
+    planned = [torch.cuda.Event() for _ in range(2)]
+    done = [torch.cuda.Event() for _ in range(2)]
+    state = {"k": 0}
 
     def run_steps(nsteps):
         """nsteps steps, each the whole path on batch k through the C ABI:
-        hygt_plan, hygt_apply forward, hygt_apply inverse, enqueued back to
-        back on one stream with no host synchronisation."""
-        for k in range(nsteps):
-            b = k % RING
-            st = _abi.hygt_plan(cp[b], NBLOCKS, LOG2N, ROUNDS, ap, NCLASSES, wp, wsb, handle)
+        hygt_plan, hygt_apply forward, hygt_apply inverse, with no host
+        synchronisation. Plans go to a second stream, into two workspaces in
+        turn, so that batch k+1 is planned while batch k is transformed: the
+        transform of a batch waits for its plan (an event), and a workspace
+        is planned again only after the transform that read it."""
+        hm, hs = main.cuda_stream, side.cuda_stream
+        for _ in range(nsteps):
+            k = state["k"]
+            b, w = k % RING, k % 2
+            if k >= 2:
+                side.wait_event(done[w])
+            st = _abi.hygt_plan(cp[b], NBLOCKS, LOG2N, ROUNDS, ap, NCLASSES, wp[w], wsb, hs)
+            planned[w].record(side)
+            main.wait_event(planned[w])
             st |= _abi.hygt_apply(xp[b], yp, NBLOCKS, LOG2N, ROUNDS, NCLASSES, _abi.HYGT_FORWARD,
-                                  wp, wsb, handle)
+                                  wp[w], wsb, hm)
             st |= _abi.hygt_apply(yp, zp, NBLOCKS, LOG2N, ROUNDS, NCLASSES, _abi.HYGT_INVERSE,
-                                  wp, wsb, handle)
+                                  wp[w], wsb, hm)
+            done[w].record(main)
             if st != _abi.HYGT_OK:
                 raise RuntimeError(f"step {k}: status {st}")
+            state["k"] = k + 1
 
-    run_steps(max(args.warmup, 1))
-    _abi._check(_abi.hygt_check_error(wp, wsb, handle), "hygt_check_error")
+    run_steps(max(args.warmup, 2))
     torch.cuda.synchronize()
+    for w in wp:
+        _abi._check(_abi.hygt_check_error(w, wsb, 0), "hygt_check_error")
     d0 = torch.cuda.Event(enable_timing=True)
     d1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
