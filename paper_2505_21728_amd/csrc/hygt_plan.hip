@@ -3,7 +3,9 @@
 //
 // Multiplier tables: one workgroup per (direction, class) runs the table
 // builder of hygt_table.h (FP64 conversion into lifting multipliers, with
-// the sign bookkeeping of the angle reduction).
+// the sign bookkeeping of the angle reduction), inside the placing launch
+// of a plan (skipped by a regrouping that keeps the tables) or, for the
+// request path, in a launch of its own (table_build_kernel).
 //
 // Grouping. A tile is 64 blocks of one class, so that a wavefront (one lane
 // per block) reads one class table with scalar loads. The blocks of each

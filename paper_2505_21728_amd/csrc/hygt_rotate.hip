@@ -25,6 +25,8 @@
 // row through a per-wavefront LDS row area after the passes (forward) or
 // before them (inverse). The fused launch for batches of several block
 // sizes (mixed_kernel) runs the same tile body over one persistent grid.
+// The request kernel (request_kernel, at the end) serves batches of requests
+// with no class grouping: its lanes follow their own classes' tables.
 //
 // Memory. The single-size kernels with N <= 64 bring a tile in through LDS
 // by DMA: each global_load_lds_dwordx4 reads the chunks of several whole
