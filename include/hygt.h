@@ -297,12 +297,14 @@ int hygt_mixed_plan(const hygt_segment* segs, int nseg, void* workspace, size_t 
 
 /* hygt_mixed_plan() without the multiplier tables: only the class grouping
  * of every segment, for callers whose angles have not changed since the
- * last hygt_mixed_plan() on this workspace with these segments' sizes (the
- * classes, the block counts and the buffers may change). The tables of that
- * plan stay in the workspace and are used as they are; with other angles, or
- * on a workspace that never held such a plan, the transform uses whatever
- * the workspace holds. A training step that changes the angles plans again
- * with hygt_mixed_plan(). */
+ * last hygt_mixed_plan() on this workspace with the same segment sizes
+ * (nblocks, log2n, rounds, nclasses of every segment, which fix where each
+ * segment's tables sit in the workspace; the classes and the x and y
+ * buffers may change). The tables of that plan stay in the workspace and
+ * are used as they are; with other angles or sizes, or on a workspace that
+ * never held such a plan, the transform uses whatever the workspace holds.
+ * A training step that changes the angles plans again with
+ * hygt_mixed_plan(). */
 int hygt_mixed_regroup(const hygt_segment* segs, int nseg, void* workspace,
                        size_t workspace_bytes, hipStream_t stream);
 

@@ -355,7 +355,8 @@ class MixedBatch:
         """Plans every segment (classes and angles as the buffers hold them
         now). tables=False only regroups the blocks by class and keeps the
         multiplier tables of the last full plan, for angles that have not
-        changed since (hygt_mixed_regroup)."""
+        changed since (hygt_mixed_regroup; the segments' sizes are fixed for
+        the object's life)."""
         torch = _torch()
         fn = _abi.hygt_mixed_plan if tables else _abi.hygt_mixed_regroup
         with torch.cuda.device(self.device):
