@@ -19,7 +19,10 @@
 // the pass before. Measured on MI355X (2^20 8x8 blocks, R = 4), this took
 // the forward transform from 119 to 112 us with the tiles in class order, and
 // made the cost of switching class tables between neighbouring tiles
-// negligible.
+// negligible. Tiles of N >= 128 stream their chunks into VGPRs instead, four
+// chunks ahead, and read each multiplier from its lane of the row by DPP
+// (VTableStream in hygt_tile.h): their few wavefronts cannot hide a scalar
+// load's L2 round trip behind each other.
 //
 // Variants. The permutation pass of Fig. 4 (N <= 64) reorders each lane's
 // row through a per-wavefront LDS row area after the passes (forward) or
@@ -97,6 +100,28 @@ __device__ __forceinline__ void lift_chunk(float (&v)[1 << D], const Chunk<F>& m
         v[mi] = fmaf(p, v[ni], v[mi]);
         v[ni] = fmaf(q, v[mi], v[ni]);
         v[mi] = fmaf(p, v[ni], v[mi]);
+    });
+}
+
+// The same with multipliers streamed into VGPRs (VChunk): the three lifting
+// steps of the chunk's pairs go in three sweeps over its 16 pairs, so that
+// the operations on one pair are 16 instructions apart, beyond the wait
+// states a DPP read needs after the write of its operands.
+template <int D, int K, int H, int F>
+__device__ __forceinline__ void lift_chunk(float (&v)[1 << D], const VChunk& m) {
+    static_assert(F == 32, "16 pairs per chunk");
+    StaticFor<0, 3>::run([&](auto st) {
+        constexpr int step = decltype(st)::value;
+        StaticFor<0, 16>::run([&](auto jj) {
+            constexpr int jl = decltype(jj)::value;
+            constexpr int j = H * 16 + jl;
+            constexpr int mi = ins0(j, K);
+            constexpr int ni = mi + (1 << K);
+            if constexpr (step == 1)
+                v[ni] = fmac_bcast<jl>(m.y, v[mi], v[ni]);
+            else
+                v[mi] = fmac_bcast<jl>(m.x, v[ni], v[mi]);
+        });
     });
 }
 
@@ -207,7 +232,7 @@ __device__ __forceinline__ void cross_pass(float (&v)[64], NextChunk&& next_chun
     StaticFor<0, 4>::run([&](auto gg) {
         constexpr int g = decltype(gg)::value;
         constexpr int buf = g & 1;
-        const Chunk<32> m = next_chunk(gg);
+        const auto m = next_chunk(gg);
         StaticFor<0, 4>::run([&](auto qq) {
             constexpr int q = decltype(qq)::value;
             constexpr int e = 16 * g + 4 * q;
@@ -223,15 +248,26 @@ __device__ __forceinline__ void cross_pass(float (&v)[64], NextChunk&& next_chun
             w[4 * q + 2] = f.z;
             w[4 * q + 3] = f.w;
         });
-        StaticFor<0, 16>::run([&](auto tt) {
-            constexpr int t = decltype(tt)::value;
-            constexpr int j = 16 * g + t;
-            const float c = m.template get<2 * t>();
-            const float sn = m.template get<2 * t + 1>();
-            // -s on the upper wavefront: a sign-bit flip
-            const float sg = __uint_as_float(__float_as_uint(sn) ^ hbit);
-            v[j] = fmaf(sg, w[t], c * v[j]);
-        });
+        if constexpr (std::is_same<std::decay_t<decltype(m)>, VChunk>::value) {
+            // -s on the upper wavefront: a sign-bit flip of the chunk's s
+            // values, then c x and the fused s x' + c x with DPP sources
+            const float sg = xor_for_dpp(m.y, hbit);
+            StaticFor<0, 16>::run([&](auto tt) {
+                constexpr int t = decltype(tt)::value;
+                constexpr int j = 16 * g + t;
+                v[j] = fmac_bcast<t>(sg, w[t], m.template get<2 * t>() * v[j]);
+            });
+        } else {
+            StaticFor<0, 16>::run([&](auto tt) {
+                constexpr int t = decltype(tt)::value;
+                constexpr int j = 16 * g + t;
+                const float c = m.template get<2 * t>();
+                const float sn = m.template get<2 * t + 1>();
+                // -s on the upper wavefront: a sign-bit flip
+                const float sg = __uint_as_float(__float_as_uint(sn) ^ hbit);
+                v[j] = fmaf(sg, w[t], c * v[j]);
+            });
+        }
     });
 }
 
@@ -260,35 +296,76 @@ __device__ __forceinline__ int64_t split_first(int64_t r, int kk, int q) {
     return off + q * V;
 }
 
+// Chunks of 16 pairs in one round of a split tile (N >= 128), in the order
+// they are used: two per pass along bits 0..5, four per pass along bits 6, 7.
 template <int D, int DIR>
+constexpr int split_pass_chunks(int kk) {
+    return (DIR == 0 ? kk : D - 1 - kk) >= kLaneBits ? 4 : 2;
+}
+template <int D, int DIR>
+constexpr int split_chunks_before(int kk) {
+    int n = 0;
+    for (int i = 0; i < kk; ++i) n += split_pass_chunks<D, DIR>(i);
+    return n;
+}
+template <int D, int DIR>
+constexpr int split_chunk_pass(int j) {
+    int kk = 0;
+    while (j >= split_pass_chunks<D, DIR>(kk)) {
+        j -= split_pass_chunks<D, DIR>(kk);
+        ++kk;
+    }
+    return kk;
+}
+
+// Chunks of multipliers in flight per wavefront of a split tile.
+constexpr int kSplitPrefetch = 4;
+
+template <int D, int DIR, int Q = kSplitPrefetch>
 __device__ __forceinline__ void run_passes_split(float (&v)[64], ctab_f tbl, ctab_f sign,
                                                  int has_neg, int rounds, int q, float4* area0,
                                                  int lane) {
     constexpr int V = 64;
-    auto first = [&](int64_t r, int kk) -> int64_t { return split_first<D, DIR>(r, kk, q); };
-    TableStream<32> ts;
-    ts.begin(tbl, first(0, 0));
+    constexpr int CR = split_chunks_before<D, DIR>(D);
+    static_assert(Q <= CR, "prefetch within the next round");
+    // table offset of chunk J of round r
+    auto off_of = [&](int64_t r, auto jj) -> int64_t {
+        constexpr int J = decltype(jj)::value;
+        constexpr int kk = split_chunk_pass<D, DIR>(J);
+        return split_first<D, DIR>(r, kk, q) + 32 * (J - split_chunks_before<D, DIR>(kk));
+    };
+    // the chunk Q after chunk J of round r (past the last: the last again)
+    auto ahead = [&](int64_t r, auto jj) -> int64_t {
+        constexpr int J = decltype(jj)::value + Q;
+        if constexpr (J < CR) {
+            return off_of(r, std::integral_constant<int, J>{});
+        } else {
+            if (r + 1 < rounds) return off_of(r + 1, std::integral_constant<int, J - CR>{});
+            return off_of(r, std::integral_constant<int, CR - 1>{});
+        }
+    };
+    VTableStream<Q> vs;
+    vs.init(reinterpret_cast<uint64_t>(tbl), lane);
+    StaticFor<0, Q>::run([&](auto ii) { vs.push(off_of(0, ii)); });
     for (int r = 0; r < rounds; ++r) {
-        const int64_t rnext = r + 1 < rounds ? r + 1 : r;
         StaticFor<0, D>::run([&](auto kk) {
             constexpr int k = decltype(kk)::value;
             constexpr int K = DIR == 0 ? k : D - 1 - k;
-            const int64_t off = first(r, k);
-            const int64_t after = k + 1 < D ? first(r, k + 1) : first(rnext, 0);
+            constexpr int j0 = split_chunks_before<D, DIR>(k);
             if constexpr (K >= kLaneBits) {
                 constexpr int b = K - kLaneBits;
                 cross_pass(
                     v,
                     [&](auto gg) {
                         constexpr int g = decltype(gg)::value;
-                        return ts.next(g + 1 < 4 ? off + 32 * (g + 1) : after);
+                        return vs.next(ahead(r, std::integral_constant<int, j0 + g>{}));
                     },
                     static_cast<unsigned>((q >> b) & 1) << 31, area0 + 512 * q,
                     area0 + 512 * (q ^ (1 << b)), lane);
             } else {
-                const Chunk<32> m0 = ts.next(off + 32);
+                const VChunk m0 = vs.next(ahead(r, std::integral_constant<int, j0>{}));
                 lift_chunk<kLaneBits, K, 0, 32>(v, m0);
-                const Chunk<32> m1 = ts.next(after);
+                const VChunk m1 = vs.next(ahead(r, std::integral_constant<int, j0 + 1>{}));
                 lift_chunk<kLaneBits, K, 1, 32>(v, m1);
             }
         });
@@ -893,28 +970,6 @@ __device__ __forceinline__ void lane_rounds(float (&v)[1 << D], const float* tbl
             lift_chunk<D, K, H, F>(v, m);
         });
     }
-}
-
-// Chunks of 16 pairs in one round of a split tile (N >= 128), in the order
-// they are used: two per pass along bits 0..5, four per pass along bits 6, 7.
-template <int D, int DIR>
-constexpr int split_pass_chunks(int kk) {
-    return (DIR == 0 ? kk : D - 1 - kk) >= kLaneBits ? 4 : 2;
-}
-template <int D, int DIR>
-constexpr int split_chunks_before(int kk) {
-    int n = 0;
-    for (int i = 0; i < kk; ++i) n += split_pass_chunks<D, DIR>(i);
-    return n;
-}
-template <int D, int DIR>
-constexpr int split_chunk_pass(int j) {
-    int kk = 0;
-    while (j >= split_pass_chunks<D, DIR>(kk)) {
-        j -= split_pass_chunks<D, DIR>(kk);
-        ++kk;
-    }
-    return kk;
 }
 
 // As run_passes_split, with a lane's own table.

@@ -21,6 +21,9 @@ constexpr int kXcds = 8;
 #define HYGT_WAVES_PER_SIMD 5
 #endif
 constexpr int kWavesPerSimd = HYGT_WAVES_PER_SIMD;
+// The same for the tiles of N >= 128, whose multiplier stream holds chunks
+// in VGPRs (VTableStream below).
+constexpr int kSplitWavesPerSimd = 4;
 
 template <int I, int End>
 struct StaticFor {
@@ -82,7 +85,7 @@ struct TileGeo {
     static constexpr int BPI = 64 / CHP;             // blocks per memory instruction
     static constexpr int WAVES = SPLIT ? SHARE : kWaves;  // wavefronts per workgroup
     static constexpr int TILES = SPLIT ? 1 : kWaves;      // tiles per workgroup
-    static constexpr int OCC = kWavesPerSimd;
+    static constexpr int OCC = SPLIT ? kSplitWavesPerSimd : kWavesPerSimd;
 };
 
 // Block id handled by memory instruction i of every part: block
@@ -270,6 +273,93 @@ struct TableStream {
             asm volatile("" : "+s"(base) : "s"(cur.a[0]), "s"(cur.a[1]));
         const Chunk<F> got = cur;
         load(off);
+        return got;
+    }
+};
+
+
+// Class tables streamed into vector registers, for the tiles of N >= 128.
+//
+// Their wavefronts are few (a tile takes 2 or 4, and small batches leave one
+// or two per SIMD) and meet at the exchange barriers, so the one-chunk-ahead
+// scalar stream above cannot hide an L2 round trip behind other wavefronts'
+// arithmetic. Here a chunk of 16 pairs takes two VGPRs: lane l holds the
+// multipliers of pair l mod 16 of the chunk (one 8-byte load per lane, 128
+// distinct bytes per wavefront), and an operation that needs pair j's
+// multiplier reads it from lane j of its row of 16 lanes through DPP
+// (row_newbcast), as a modifier of the operation itself. Vector loads return
+// in order, so the stream keeps Q chunks in flight and waits only for the
+// oldest. Measured on MI355X (2^15 16x16 blocks, R = 4): 46 -> 38 us; the
+// same stream for N <= 64, where the VALU work dominates, was slower
+// (126 -> 137 us at 2^20 8x8 blocks), so those tiles keep the scalar stream.
+
+// a + m[lane J of this lane's row] * b, one v_fmac_f32 with a DPP source.
+// The compiler cannot fuse a DPP move into a multiply-accumulate by itself
+// (it does for multiplies and adds); the two wait states that a DPP read
+// needs after a VALU write of its operands are checked on the built code.
+template <int J>
+__device__ __forceinline__ float fmac_bcast(float m, float b, float a) {
+    static_assert(J >= 0 && J < 16, "lane of a row");
+    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(a)
+        : "v"(m), "v"(b), "i"(J));
+    return a;
+}
+
+// x ^ bits for a DPP source: the two wait states before any DPP read of the
+// result are part of the same statement.
+__device__ __forceinline__ float xor_for_dpp(float x, unsigned bits) {
+    float out;
+    asm("v_xor_b32 %0, %1, %2\n\ts_nop 1" : "=v"(out) : "s"(bits), "v"(x));
+    return out;
+}
+
+struct VChunk {
+    float x, y;  // lane l: the two floats of pair l mod 16 of the chunk
+    // float I of the chunk (2j: first multiplier of pair j, 2j + 1: second)
+    // in every lane, through a DPP move that the compiler fuses into the
+    // multiply or add that uses it
+    template <int I>
+    __device__ __forceinline__ float get() const {
+        constexpr int j = I / 2;
+        static_assert(j < 16, "pairs per chunk");
+        const float f = (I & 1) ? y : x;
+        return __int_as_float(
+            __builtin_amdgcn_mov_dpp(__float_as_int(f), 0x150 + j, 0xf, 0xf, true));
+    }
+};
+
+template <int Q>
+struct VTableStream {
+    typedef float vf2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) vf2* GP;
+    uint64_t base;   // table address, rewritten (unchanged) by every next()
+    uint32_t pair;   // lane mod 16
+    float bx[Q], by[Q];  // chunks in flight, oldest first
+    __device__ __forceinline__ void init(uint64_t table, int lane) {
+        base = table;
+        pair = static_cast<uint32_t>(lane) & 15;
+    }
+    // Requests the 32 floats at `off` (floats from the table start) behind
+    // those in flight.
+    __device__ __forceinline__ void push(int64_t off) {
+        StaticFor<0, Q - 1>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            bx[i] = bx[i + 1];
+            by[i] = by[i + 1];
+        });
+        const GP p = reinterpret_cast<GP>(base + static_cast<uint64_t>(off) * sizeof(float));
+        const vf2 f = p[pair];
+        bx[Q - 1] = f.x;
+        by[Q - 1] = f.y;
+    }
+    // Returns the oldest chunk and requests the one at `off`. The empty asm
+    // statement makes the compiler wait for that chunk here, and the next
+    // load, addressed from the rewritten pointer, cannot be issued earlier.
+    __device__ __forceinline__ VChunk next(int64_t off) {
+        asm volatile("" : "+s"(base) : "v"(bx[0]), "v"(by[0]));
+        const VChunk got{bx[0], by[0]};
+        push(off);
         return got;
     }
 };

@@ -14,6 +14,11 @@ its gfx950 code object, which is disassembled and its kernel metadata read.
   vector memory operations. That is right only if at least 8 of them were
   issued after the last DMA instruction; every such wait in the built code
   is checked for it.
+- Every DPP instruction has the wait states the ISA requires before it: 2
+  after a VALU write of any VGPR it reads and 5 after a write of EXEC, on
+  every path that reaches it (branches and loop back edges included). Some
+  of these instructions are written as inline assembly (hygt_tile.h), where
+  the compiler does not know that they are DPP.
 """
 
 import os
@@ -123,3 +128,89 @@ def test_dma_wait_counts(code_objects):
             waits += 1
             assert after_dma >= 8, f"{co.name}: only {after_dma} operations after the DMA"
     assert waits > 0   # the tile loads of N = 64 were found
+
+
+_INSTR = re.compile(r"^\s+(\w+)\s*([^/]*?)\s*//\s*([0-9A-Fa-f]+):")
+_SYMBOL = re.compile(r"^([0-9a-f]+) <(\S+)>:$")
+_TARGET = re.compile(r"<(\S+?)\+0x([0-9a-f]+)>")
+
+
+def _vgprs(operand):
+    m = re.fullmatch(r"v(\d+)", operand)
+    if m:
+        return {int(m.group(1))}
+    m = re.fullmatch(r"v\[(\d+):(\d+)\]", operand)
+    if m:
+        return set(range(int(m.group(1)), int(m.group(2)) + 1))
+    return set()
+
+
+def _instructions(text):
+    """(mnemonic, operands, address, branch target address or None) per
+    instruction of a disassembly, in address order."""
+    symbols = {}
+    out = []
+    for line in text.splitlines():
+        m = _SYMBOL.match(line)
+        if m:
+            symbols[m.group(2)] = int(m.group(1), 16)
+            continue
+        m = _INSTR.match(line)
+        if not m:
+            continue
+        ops = [o.strip().split()[0] for o in m.group(2).split(",") if o.strip()]
+        target = None
+        t = _TARGET.search(line)
+        if t and m.group(1).startswith(("s_branch", "s_cbranch")):
+            target = symbols[t.group(1)] + int(t.group(2), 16)
+        out.append((m.group(1), ops, int(m.group(3), 16), target))
+    return out
+
+
+def test_dpp_wait_states(code_objects):
+    objdump = _tool("llvm-objdump")
+    checked = 0
+    for co in code_objects:
+        text = subprocess.run([objdump, "-d", str(co)], check=True, capture_output=True,
+                              text=True).stdout
+        ins = _instructions(text)
+        index = {addr: i for i, (_, _, addr, _) in enumerate(ins)}
+        into = {}  # instruction index -> indices of the branches to it
+        for i, (_, _, _, target) in enumerate(ins):
+            if target is not None and target in index:
+                into.setdefault(index[target], []).append(i)
+
+        def preds(i):
+            out = list(into.get(i, []))
+            if i > 0 and ins[i - 1][0] not in ("s_branch", "s_endpgm", "s_setpc_b64"):
+                out.append(i - 1)
+            return out
+
+        for k, (op, ops, addr, _) in enumerate(ins):
+            if not op.endswith("_dpp"):
+                continue
+            checked += 1
+            reads = set().union(*(_vgprs(o) for o in ops))
+            # walk back over every path, counting wait states
+            todo = [(j, 0) for j in preds(k)]
+            seen = set()
+            while todo:
+                j, ws = todo.pop()
+                if (j, ws) in seen or ws >= 5:
+                    continue
+                seen.add((j, ws))
+                pop, pops, paddr, _ = ins[j]
+                where = f"{co.name}: {op} at {addr:#x} after {pop} at {paddr:#x}"
+                if pop == "s_nop":
+                    cost = int(pops[0], 0) + 1
+                else:
+                    cost = 1
+                    valu_vgpr = (pop.startswith("v_") and pops and not pop.startswith(
+                        ("v_cmp", "v_readlane", "v_readfirstlane")))
+                    if ws < 2 and valu_vgpr:
+                        assert not (_vgprs(pops[0]) & reads), "VALU write -> DPP read: " + where
+                    writes_exec = ("saveexec" in pop or pop.startswith("v_cmpx")
+                                   or (pops and pops[0].startswith("exec")))
+                    assert not writes_exec, "EXEC write -> DPP: " + where
+                todo.extend((p, ws + cost) for p in preds(j))
+    assert checked > 1000  # the split tiles' passes were found
