@@ -73,6 +73,9 @@ def _args():
                     help="only run plain 256 MiB device copies (HBM counter calibration)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed steps and the kernel rooflines (for counter runs)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only the mixed-size workload, printed as one JSON line (for "
+                         "counter runs of the fused launch)")
     return ap.parse_args()
 
 
@@ -468,7 +471,7 @@ def main():
     from paper_2505_21728_amd import synth
 
     ang = x = cls = cpu = None
-    if not args.copy_calibration:
+    if not (args.copy_calibration or args.mixed_only):
         ang = synth.angles(NCLASSES, ROUNDS, LOG2N)
         x = synth.ar1_blocks(NBLOCKS, 8)
         cls = synth.classes(NBLOCKS, NCLASSES)
@@ -483,6 +486,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         _copy_calibration(torch, dev)
+        return
+    if args.mixed_only:
+        print(json.dumps({"mixed": _mixed_workload(torch, hygt, args.steps)}))
         return
 
     x0 = torch.from_numpy(x).to(dev)
