@@ -459,7 +459,7 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
     const int blk = c < 0 ? -1 : valid_block(perm[t0 * kTile + lane], nblocks);
     float v[G::V];
     if constexpr (TILE_LOAD && !G::SPLIT) {
-        if (c >= 0) load_tile<D>(xh, blk, v, L, lane);
+        if (c >= 0) load_tile<D, DIR == 1 && D == kLaneBits>(xh, blk, v, L, lane);
     } else {
         load_row<D>(xh, blk, v);
     }

@@ -151,7 +151,17 @@ __device__ __forceinline__ void load_row(const float* __restrict__ x, int blk, f
 // (blk < 0) read block 0, which exists whenever a launch has blocks, and
 // drop it: every load is issued, so the wait below counts exactly. L: the
 // wavefront's LDS area of at least 64 * min(N/4, 8) float4.
-template <int D>
+//
+// With PRIO the loads are issued at the highest wavefront priority, so that
+// other wavefronts' arithmetic does not hold them back. For N = 64 the
+// inverse transform starts with the pass along bit 5, which pairs values
+// from both halves of a block and so can start only once the whole tile is
+// in; measured on MI355X (2^20 8x8 blocks, R = 4), this took its launch from
+// 113.4 to 110.3 us, while the forward, which starts on the DMA half, lost
+// about 1 us and issues its loads at normal priority. For N <= 32 (one DMA
+// round trip in either direction) the inverse gained 1 us at N = 16 but lost
+// 4 us at N = 8 (2^21 blocks), so only the inverse of N = 64 uses it.
+template <int D, bool PRIO = false>
 __device__ __forceinline__ void load_tile(const float* __restrict__ x, int blk, float* v,
                                           float4* L, int lane) {
     using G = TileGeo<D>;
@@ -166,6 +176,7 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ x, int blk, 
         constexpr int i = decltype(ii)::value;
         bb[i] = __builtin_amdgcn_ds_bpermute((i * BPI + lane / CD) << 2, src);
     });
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
 #if defined(__HIP_DEVICE_COMPILE__)  // the LDS-DMA builtin exists only in the device pass
     StaticFor<0, CD>::run([&](auto ii) {
         constexpr int i = decltype(ii)::value;
@@ -188,10 +199,12 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ x, int blk, 
             v[4 * q + 2] = f.z;
             v[4 * q + 3] = f.w;
         });
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         // the DMA loads are older than the CH - CD row loads
         static_assert(CH - CD == 8, "N = 64");
         asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
     } else {
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     StaticFor<0, CD>::run([&](auto qq) {
