@@ -317,8 +317,9 @@ static_assert(sizeof(RequestArgs) <= 4096, "kernel arguments");
 
 // Workgroups (of four wavefronts) of a request of nblocks blocks of 2^log2n
 // values: four tiles of 64 blocks per workgroup for N <= 64, two for
-// N = 128, one for N = 256.
+// N = 128; for N = 256 four blocks (a wavefront each).
 inline int64_t request_workgroups(int64_t nblocks, int log2n) {
+    if (log2n == 8) return (nblocks + 3) / 4;  // a wavefront per block
     const int64_t tiles = (nblocks + kTile - 1) / kTile;
     const int64_t per = log2n > kLaneBits ? 4 >> (log2n - kLaneBits) : 4;
     return (tiles + per - 1) / per;

@@ -1023,10 +1023,10 @@ __device__ __forceinline__ void lane_passes_split(float (&v)[64], const float* t
     }
 }
 
-// Local workgroup lw of a request of N = 2^D blocks: tiles of 64 consecutive
-// blocks, four per workgroup (a wavefront each) for N <= 64, two for N = 128
-// and one for N = 256 (2^(D-6) wavefronts each, wavefront q holding values
-// 64q .. 64q+63 of every block). A lane loads its block's class; one outside
+// Local workgroup lw of a request of N = 2^D blocks, N <= 128: tiles of 64
+// consecutive blocks, four per workgroup (a wavefront each) for N <= 64, two
+// for N = 128 (two wavefronts each, wavefront q holding values 64q .. 64q+63
+// of every block). A lane loads its block's class; one outside
 // [0, nclasses) sets the request's status, runs with class 0's table and
 // writes zeros. The tiles of a workgroup of N >= 128 pass the same
 // barriers, a tile past the request's end included (it touches no block).
@@ -1093,6 +1093,126 @@ __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __
     });
 }
 
+// Requests of N = 256: a wavefront per block, lane l holding elements
+// 4l .. 4l+3 (one 16-byte load and store per lane, 1 KB per wavefront). The
+// block's class is wave-uniform, so the multipliers of a pass are one
+// coalesced read of the class table: a pass along bit 0 or 1 pairs values
+// inside a lane (pairs 2l and 2l+1 of the pass, four floats); a pass along
+// bit K >= 2 pairs lane l with lane l ^ 2^(K-2), value by value, and lane l
+// reads the multipliers of pairs 4l' .. 4l'+3 (l' = l without bit K-2). Each
+// lane of such a pair fetches its partner's value and runs the pair's whole
+// lifting (bits < 6) or its own half of the (cos, sin) step (bits 6, 7) with
+// the same FMAs, operands and order as the grouped tiles, so results are
+// bit-identical to theirs; it keeps its own output. Lane-per-block tiles of
+// N = 256 take every multiplier as a per-lane 16-byte load from its block's
+// table and keep a request of 8192 blocks on 512 wavefronts; this layout
+// moves the same table bytes in whole rows and gives that request 8192
+// wavefronts. Multipliers are read one pass ahead.
+//
+// Multipliers of pass kk (application order) of round r for this lane: two
+// float4 (the first only, for passes along bits 0 and 1).
+template <int DIR>
+__device__ __forceinline__ void mult256(const float* tbl, int64_t r, int kk, int lane,
+                                        float4& m0, float4& m1) {
+    const int K = DIR == 0 ? kk : 7 - kk;
+    const float* pass = tbl + (r * 8 + kk) * 256;
+    if (K < 2) {
+        m0 = reinterpret_cast<const float4*>(pass)[lane];
+        m1 = m0;
+    } else {
+        const int b = K - 2;
+        const int lr = ((lane >> (b + 1)) << b) | (lane & ((1 << b) - 1));
+        const float4* q = reinterpret_cast<const float4*>(pass + 8 * lr);
+        m0 = q[0];
+        m1 = q[1];
+    }
+}
+
+__device__ __forceinline__ void lift_pair(float& a, float& b, float p, float q) {
+    a = fmaf(p, b, a);
+    b = fmaf(q, a, b);
+    a = fmaf(p, b, a);
+}
+
+template <int DIR>
+__device__ __forceinline__ void request_block256(const ReqTable& tb, const float* __restrict__ x,
+                                                 float* __restrict__ y,
+                                                 const int32_t* __restrict__ cls,
+                                                 int64_t nblocks, int64_t lw, int wv, int lane,
+                                                 int32_t* status) {
+    constexpr int N = 256;
+    const int64_t blk = lw * 4 + wv;
+    if (blk >= nblocks) return;  // no barrier on this path
+    int c = cls != nullptr ? __builtin_amdgcn_readfirstlane(cls[blk]) : 0;
+    const bool bad = c < 0 || c >= tb.nclasses;
+    if (bad) {
+        // the ring is in host memory: a system-scope store, which no cache
+        // between the device and that memory holds back
+        if (lane == 0)
+            __hip_atomic_store(status, static_cast<int32_t>(HYGT_ECLASS), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        c = 0;
+    }
+    const size_t table = static_cast<size_t>(DIR) * tb.nclasses + c;
+    const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * 8 * N;
+    const float4 in = reinterpret_cast<const float4*>(x + blk * N)[lane];
+    float v[4] = {in.x, in.y, in.z, in.w};
+    float4 m0, m1;
+    mult256<DIR>(tbl, 0, 0, lane, m0, m1);
+    for (int r = 0; r < tb.rounds; ++r) {
+        StaticFor<0, 8>::run([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            constexpr int K = DIR == 0 ? k : 7 - k;
+            const float4 a0 = m0, a1 = m1;
+            // the next pass's multipliers (past the last pass: the last again)
+            if (k + 1 < 8)
+                mult256<DIR>(tbl, r, k + 1, lane, m0, m1);
+            else
+                mult256<DIR>(tbl, r + 1 < tb.rounds ? r + 1 : r, r + 1 < tb.rounds ? 0 : 7,
+                             lane, m0, m1);
+            if constexpr (K == 0) {
+                lift_pair(v[0], v[1], a0.x, a0.y);
+                lift_pair(v[2], v[3], a0.z, a0.w);
+            } else if constexpr (K == 1) {
+                lift_pair(v[0], v[2], a0.x, a0.y);
+                lift_pair(v[1], v[3], a0.z, a0.w);
+            } else {
+                constexpr int mask = 1 << (K - 2);
+                const bool hi = (lane & mask) != 0;
+                float w[4];
+                StaticFor<0, 4>::run([&](auto ii) {
+                    constexpr int i = decltype(ii)::value;
+                    w[i] = __shfl_xor(v[i], mask, 64);
+                });
+                const float mm[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+                StaticFor<0, 4>::run([&](auto ii) {
+                    constexpr int i = decltype(ii)::value;
+                    const float p = mm[2 * i], q = mm[2 * i + 1];
+                    if constexpr (K < kLaneBits) {
+                        float a = hi ? w[i] : v[i];
+                        float b = hi ? v[i] : w[i];
+                        lift_pair(a, b, p, q);
+                        v[i] = hi ? b : a;
+                    } else {
+                        // (cos, sin): y_m = c x_m + s x_n, y_n = c x_n - s x_m
+                        const float sg = hi ? -q : q;
+                        v[i] = fmaf(sg, w[i], p * v[i]);
+                    }
+                });
+            }
+        });
+    }
+    if (tb.modes[table]) {
+        const float4 sg = reinterpret_cast<const float4*>(tb.signs + table * N)[lane];
+        v[0] *= sg.x;
+        v[1] *= sg.y;
+        v[2] *= sg.z;
+        v[3] *= sg.w;
+    }
+    if (bad) v[0] = v[1] = v[2] = v[3] = 0.0f;
+    store_nt(y + blk * N + 4 * lane, make_float4(v[0], v[1], v[2], v[3]));
+}
+
 // The address u, of global memory, as a pointer that the compiler knows to
 // be global (made from the integer as a global pointer, then converted), so
 // that every access derived from it is a global rather than a generic
@@ -1150,7 +1270,7 @@ __global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
         case 5: request_tile<5, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 6: request_tile<6, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 7: request_tile<7, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 8: request_tile<8, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
+        case 8: request_block256<DIR>(tb, x, y, cls, nblocks, lw, wv, lane, status); break;
         default: break;
     }
 }
