@@ -293,8 +293,8 @@ struct ReqDesc {
     const int32_t* cls;
     int32_t nblocks;   // <= 2^26
     int32_t table;
-    int32_t first_wg;  // first workgroup of the request in the launch
-    int32_t pad;
+    int32_t first_wg;  // first workgroup of the request in its launch
+    int32_t entry;     // its ring entry: first + entry (mod capacity)
 };
 
 // Arguments of a request launch (hygt_rotate.hip): the batch's descriptors
@@ -325,8 +325,11 @@ inline int64_t request_workgroups(int64_t nblocks, int log2n) {
     return (tiles + per - 1) / per;
 }
 
-hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, int direction,
-                           hipStream_t stream);
+// Requests of N <= 128 (a) and of N = 256 (wide) go to two launches: the
+// wide requests' kernel needs few registers and runs many wavefronts per
+// SIMD, which the other kernel's register budget would not allow.
+hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, const RequestArgs& wide,
+                           int64_t wide_workgroups, int direction, hipStream_t stream);
 
 // Dense per-class transform (hygt_dense.hip), N = 64.
 hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,

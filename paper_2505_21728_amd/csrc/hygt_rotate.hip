@@ -1223,19 +1223,24 @@ __device__ __forceinline__ T* global_ptr(uint64_t u) {
     return (T*)reinterpret_cast<G>(u);
 }
 
-// Workgroup w belongs to the last of the batch's requests whose first
-// workgroup is <= w (first_wg is non-decreasing along the batch, and a
+// Workgroup w belongs to the last of the launch's requests whose first
+// workgroup is <= w (first_wg is non-decreasing along the launch, and a
 // request without blocks shares its first workgroup with the next one),
 // found by a binary search over the descriptors in the kernel's argument
 // segment (wave-uniform scalar loads).
-template <int DIR>
-__global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
-    __shared__ float4 lds[4][512];
+struct ReqWork {
+    ReqTable tb;
+    const float* x;
+    float* y;
+    const int32_t* cls;
+    int64_t nblocks;
+    int64_t lw;        // workgroup of the request
+    int32_t* status;   // the request's ring entry's status
+};
+
+__device__ __forceinline__ ReqWork locate_request(const RequestArgs& a, int w) {
     typedef const __attribute__((address_space(4))) RequestArgs* ArgPtr;
     const ArgPtr pa = (ArgPtr)__builtin_amdgcn_kernarg_segment_ptr();
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int w = blockIdx.x;
     int lo = 0, hi = a.count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1243,26 +1248,50 @@ __global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
         else hi = mid - 1;
     }
     const int r = lo;
-    const uint64_t ex = reinterpret_cast<uint64_t>(pa->req[r].x);
-    const uint64_t ey = reinterpret_cast<uint64_t>(pa->req[r].y);
+    ReqWork o;
     const uint64_t ec = reinterpret_cast<uint64_t>(pa->req[r].cls);
-    const int64_t nblocks = pa->req[r].nblocks;
-    const int64_t lw = w - pa->req[r].first_wg;
-    int64_t idx = a.first + r;
+    o.x = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->req[r].x));
+    o.y = global_ptr<float>(reinterpret_cast<uint64_t>(pa->req[r].y));
+    o.cls = ec ? global_ptr<const int32_t>(ec) : nullptr;
+    o.nblocks = pa->req[r].nblocks;
+    o.lw = w - pa->req[r].first_wg;
+    int64_t idx = a.first + pa->req[r].entry;
     if (idx >= a.capacity) idx -= a.capacity;
-    int32_t* status = a.status + 12 * idx;
+    o.status = a.status + 12 * idx;
     const int ti = pa->req[r].table;
-    ReqTable tb;
-    tb.modes = global_ptr<const int32_t>(reinterpret_cast<uint64_t>(pa->tab[ti].modes));
-    tb.coef = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->tab[ti].coef));
-    tb.signs = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->tab[ti].signs));
-    tb.log2n = pa->tab[ti].log2n;
-    tb.rounds = pa->tab[ti].rounds;
-    tb.nclasses = pa->tab[ti].nclasses;
-    tb.pad = 0;
-    const float* x = global_ptr<const float>(ex);
-    float* y = global_ptr<float>(ey);
-    const int32_t* cls = ec ? global_ptr<const int32_t>(ec) : nullptr;
+    o.tb.modes = global_ptr<const int32_t>(reinterpret_cast<uint64_t>(pa->tab[ti].modes));
+    o.tb.coef = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->tab[ti].coef));
+    o.tb.signs = global_ptr<const float>(reinterpret_cast<uint64_t>(pa->tab[ti].signs));
+    o.tb.log2n = pa->tab[ti].log2n;
+    o.tb.rounds = pa->tab[ti].rounds;
+    o.tb.nclasses = pa->tab[ti].nclasses;
+    o.tb.pad = 0;
+    return o;
+}
+
+// Requests of N = 256 (wavefront per block).
+template <int DIR>
+__global__ __launch_bounds__(256) void request_wide_kernel(RequestArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const ReqWork o = locate_request(a, blockIdx.x);
+    request_block256<DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status);
+}
+
+// Requests of N <= 128.
+template <int DIR>
+__global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
+    __shared__ float4 lds[4][512];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const ReqWork o = locate_request(a, blockIdx.x);
+    const ReqTable& tb = o.tb;
+    const float* x = o.x;
+    float* y = o.y;
+    const int32_t* cls = o.cls;
+    const int64_t nblocks = o.nblocks;
+    const int64_t lw = o.lw;
+    int32_t* status = o.status;
     switch (tb.log2n) {
         case 2: request_tile<2, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 3: request_tile<3, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
@@ -1270,22 +1299,32 @@ __global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
         case 5: request_tile<5, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 6: request_tile<6, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 7: request_tile<7, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 8: request_block256<DIR>(tb, x, y, cls, nblocks, lw, wv, lane, status); break;
         default: break;
     }
 }
 
 }  // namespace
 
-hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, int direction,
-                           hipStream_t stream) {
-    if (workgroups <= 0) return hipSuccess;
-    const dim3 grid(static_cast<unsigned>(workgroups));
-    if (direction == 0)
-        hipLaunchKernelGGL((request_kernel<0>), grid, dim3(256), 0, stream, a);
-    else
-        hipLaunchKernelGGL((request_kernel<1>), grid, dim3(256), 0, stream, a);
-    return hipGetLastError();
+hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, const RequestArgs& wide,
+                           int64_t wide_workgroups, int direction, hipStream_t stream) {
+    if (workgroups > 0) {
+        const dim3 grid(static_cast<unsigned>(workgroups));
+        if (direction == 0)
+            hipLaunchKernelGGL((request_kernel<0>), grid, dim3(256), 0, stream, a);
+        else
+            hipLaunchKernelGGL((request_kernel<1>), grid, dim3(256), 0, stream, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (wide_workgroups > 0) {
+        const dim3 grid(static_cast<unsigned>(wide_workgroups));
+        if (direction == 0)
+            hipLaunchKernelGGL((request_wide_kernel<0>), grid, dim3(256), 0, stream, wide);
+        else
+            hipLaunchKernelGGL((request_wide_kernel<1>), grid, dim3(256), 0, stream, wide);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace hygt

@@ -1,15 +1,17 @@
 """The request path (hygt_table_build + hygt_requests_apply, Sec. IV eq. (5),
 (6), (9)) through the C ABI with device data, against the FP64 oracle.
 
-One launch transforms a run of ring entries of different block sizes (N = 4
-to 256), ragged block counts (1, 63, 64, 65, ...) and an empty request; the
+One call transforms a run of ring entries of different block sizes (N = 4
+to 256; the requests of N = 256 in a second launch of their own, a
+wavefront per block), ragged block counts (1, 63, 64, 65, ...) and an
+empty request; the
 ring wraps around (the run starts near its end); one request runs in place
 and one has a single class with cls = NULL. Each output matches the oracle
 (relative L2 <= 1e-5 per block and over the request, on sampled blocks) and,
 bit for bit, hygt_plan + hygt_apply on the same blocks, in both directions.
 A request with class indices out of range gets HYGT_ECLASS in its ring
-entry and zeros in those blocks; the other requests of its launch are not
-affected."""
+entry and zeros in those blocks, in either launch; the other requests of
+the call are not affected."""
 
 import sys
 
@@ -160,19 +162,24 @@ def test_requests_match_oracle_and_plan(launch):
 
 
 def test_request_with_bad_classes_is_flagged_and_zeroed():
+    """Bad classes in a request of N = 16 and in one of N = 256 (which runs
+    in the batch's second launch): each flags its own ring entry."""
     dev = _dev()
-    specs = [(6, 4, 35), (4, 2, 7)]
+    specs = [(6, 4, 35), (4, 2, 7), (8, 2, 5)]
     tabs = _tables(specs, dev, seed=900)
     refs = _abi.table_refs([(tb.data_ptr(), d, r, c) for (d, r, c), (_, _, tb)
                             in zip(specs, tabs)])
-    mem, ring = _ring(4)
+    mem, ring = _ring(6)
     data = []
-    for i, (ti, nb) in enumerate([(0, 300), (1, 100), (0, 70)]):
+    reqs = [(0, 300), (1, 100), (0, 70), (2, 50), (2, 20)]
+    for i, (ti, nb) in enumerate(reqs):
         d, r, c = specs[ti]
         x = _blocks(nb, d, seed=910 + i)
         cls = synth.classes(nb, c, seed=920 + i)
         if i == 1:
             cls[[0, 5, 99]] = [c, -1, 1 << 20]    # out of range
+        if i == 3:
+            cls[[1, 49]] = [c, -2]
         xt = torch.from_numpy(x).to(dev)
         ct = torch.from_numpy(cls).to(dev)
         yt = torch.full_like(xt, 7.0)           # stale contents
@@ -180,9 +187,9 @@ def test_request_with_bad_classes_is_flagged_and_zeroed():
         e["x"], e["y"], e["cls"] = xt.data_ptr(), yt.data_ptr(), ct.data_ptr()
         e["nblocks"], e["table"], e["status"] = nb, ti, 0
         data.append((ti, x, cls, yt, xt, ct))     # the inputs stay alive until the launch ends
-    _say("requests: bad classes in request 1 of 3")
-    _apply(mem, 4, 0, 3, refs, 2, _abi.HYGT_FORWARD)
-    assert list(ring["status"][:3]) == [0, _abi.HYGT_ECLASS, 0]
+    _say("requests: bad classes in requests 1 and 3 of 5")
+    _apply(mem, 6, 0, len(reqs), refs, 3, _abi.HYGT_FORWARD)
+    assert list(ring["status"][:5]) == [0, _abi.HYGT_ECLASS, 0, _abi.HYGT_ECLASS, 0]
     for i, (ti, x, cls, yt, _, _) in enumerate(data):
         d, r, c = specs[ti]
         ang = tabs[ti][0]
