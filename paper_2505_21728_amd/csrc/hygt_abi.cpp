@@ -575,14 +575,15 @@ int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int
     // The batch's descriptors go to the launch by value (the kernel reads
     // them from its argument segment); only the statuses are written back
     // into the ring by the device.
-    // Requests of N = 256 go to a launch of their own (`wide`), the others
-    // keep their order in `a`; first_wg counts each launch's workgroups.
+    // Requests of N >= 64 go to a launch of their own (`wide`, a wavefront
+    // per block), the others keep their order in `a`; first_wg counts each
+    // launch's workgroups.
     hygt::RequestArgs wide = a;
     int64_t wgs = 0, wide_wgs = 0;
     int na = 0, nw = 0;
     for (int i = 0; i < count; ++i) {
         hygt_request& e = ring[(first + i) % capacity];
-        const bool is_wide = tables[e.table].log2n == 8;
+        const bool is_wide = tables[e.table].log2n >= hygt::kLaneBits;
         int64_t& w = is_wide ? wide_wgs : wgs;
         e.first_wg = w;
         hygt::ReqDesc& q = is_wide ? wide.req[nw++] : a.req[na++];

@@ -316,18 +316,16 @@ struct RequestArgs {
 static_assert(sizeof(RequestArgs) <= 4096, "kernel arguments");
 
 // Workgroups (of four wavefronts) of a request of nblocks blocks of 2^log2n
-// values: four tiles of 64 blocks per workgroup for N <= 64, two for
-// N = 128; for N = 256 four blocks (a wavefront each).
+// values: four tiles of 64 blocks for N <= 32; for N >= 64 four blocks, a
+// wavefront each.
 inline int64_t request_workgroups(int64_t nblocks, int log2n) {
-    if (log2n == 8) return (nblocks + 3) / 4;  // a wavefront per block
-    const int64_t tiles = (nblocks + kTile - 1) / kTile;
-    const int64_t per = log2n > kLaneBits ? 4 >> (log2n - kLaneBits) : 4;
-    return (tiles + per - 1) / per;
+    if (log2n >= kLaneBits) return (nblocks + 3) / 4;
+    return ((nblocks + kTile - 1) / kTile + 3) / 4;
 }
 
-// Requests of N <= 128 (a) and of N = 256 (wide) go to two launches: the
-// wide requests' kernel needs few registers and runs many wavefronts per
-// SIMD, which the other kernel's register budget would not allow.
+// Requests of N <= 32 (a) and of N >= 64 (wide: a wavefront per block) go
+// to two launches: each kernel then has the register budget of its own
+// paths only.
 hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, const RequestArgs& wide,
                            int64_t wide_workgroups, int direction, hipStream_t stream);
 

@@ -972,64 +972,10 @@ __device__ __forceinline__ void lane_rounds(float (&v)[1 << D], const float* tbl
     }
 }
 
-// As run_passes_split, with a lane's own table.
-template <int D, int DIR>
-__device__ __forceinline__ void lane_passes_split(float (&v)[64], const float* tbl, int rounds,
-                                                  int q, float4* area0, int lane) {
-    constexpr int CR = split_chunks_before<D, DIR>(D);
-    // table offset of chunk J of round r
-    auto off_of = [&](int64_t r, auto jj) -> int64_t {
-        constexpr int J = decltype(jj)::value;
-        constexpr int kk = split_chunk_pass<D, DIR>(J);
-        return split_first<D, DIR>(r, kk, q) + 32 * (J - split_chunks_before<D, DIR>(kk));
-    };
-    // the chunk P after chunk J of round r (past the last: the last again)
-    constexpr int P = kLanePrefetch;
-    static_assert(P <= CR, "prefetch within the next round");
-    auto ahead = [&](int64_t r, auto jj) -> int64_t {
-        constexpr int J = decltype(jj)::value + P;
-        if constexpr (J < CR) {
-            return off_of(r, std::integral_constant<int, J>{});
-        } else {
-            if (r + 1 < rounds) return off_of(r + 1, std::integral_constant<int, J - CR>{});
-            return off_of(r, std::integral_constant<int, CR - 1>{});
-        }
-    };
-    LaneStream<32> ls;
-    // the first P chunks of round 0 (CR >= P: no round holds fewer)
-    ls.begin(tbl, [&](auto ii) -> int64_t { return off_of(0, ii); });
-    for (int r = 0; r < rounds; ++r) {
-        StaticFor<0, D>::run([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            constexpr int K = DIR == 0 ? k : D - 1 - k;
-            constexpr int j0 = split_chunks_before<D, DIR>(k);
-            if constexpr (K >= kLaneBits) {
-                constexpr int b = K - kLaneBits;
-                cross_pass(
-                    v,
-                    [&](auto gg) {
-                        constexpr int g = decltype(gg)::value;
-                        return ls.next(ahead(r, std::integral_constant<int, j0 + g>{}));
-                    },
-                    static_cast<unsigned>((q >> b) & 1) << 31, area0 + 512 * q,
-                    area0 + 512 * (q ^ (1 << b)), lane);
-            } else {
-                const Chunk<32> m0 = ls.next(ahead(r, std::integral_constant<int, j0>{}));
-                lift_chunk<kLaneBits, K, 0, 32>(v, m0);
-                const Chunk<32> m1 = ls.next(ahead(r, std::integral_constant<int, j0 + 1>{}));
-                lift_chunk<kLaneBits, K, 1, 32>(v, m1);
-            }
-        });
-    }
-}
-
-// Local workgroup lw of a request of N = 2^D blocks, N <= 128: tiles of 64
-// consecutive blocks, four per workgroup (a wavefront each) for N <= 64, two
-// for N = 128 (two wavefronts each, wavefront q holding values 64q .. 64q+63
-// of every block). A lane loads its block's class; one outside
-// [0, nclasses) sets the request's status, runs with class 0's table and
-// writes zeros. The tiles of a workgroup of N >= 128 pass the same
-// barriers, a tile past the request's end included (it touches no block).
+// Local workgroup lw of a request of N = 2^D blocks, N <= 32: four tiles
+// of 64 consecutive blocks, a wavefront each. A lane loads its block's
+// class; one outside [0, nclasses) sets the request's status, runs with
+// class 0's table and writes zeros.
 template <int D, int DIR>
 __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __restrict__ x,
                                              float* __restrict__ y,
@@ -1037,16 +983,14 @@ __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __
                                              int64_t lw, int wv, int lane, float4 (*lds)[512],
                                              int32_t* status) {
     using G = TileGeo<D>;
+    static_assert(!G::SPLIT && D <= 5, "one lane per block");
     constexpr int N = G::N;
-    constexpr int S = G::SHARE;
-    constexpr int V = G::V;
     constexpr int CHP = G::CHP;
-    const int q = wv % S;
-    const int64_t t = lw * (4 / S) + wv / S;
+    const int64_t t = lw * 4 + wv;
     const int64_t ntiles = (nblocks + kTile - 1) / kTile;
-    if (!G::SPLIT && t >= ntiles) return;
+    if (t >= ntiles) return;
     const int64_t b64 = t * kTile + lane;
-    const int blk = (t < ntiles && b64 < nblocks) ? static_cast<int>(b64) : -1;
+    const int blk = b64 < nblocks ? static_cast<int>(b64) : -1;
     int c = 0;
     if (blk >= 0 && cls != nullptr) c = cls[blk];
     const bool bad = blk >= 0 && (c < 0 || c >= tb.nclasses);
@@ -1059,27 +1003,19 @@ __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __
     }
     const size_t table = static_cast<size_t>(DIR) * tb.nclasses + c;
     const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * D * N;
-    float v[V];
-    if constexpr (G::SPLIT) {
-        load_row<D>(x + q * V, blk, v);
-        lane_passes_split<D, DIR>(v, tbl, tb.rounds, q, lds[wv - q], lane);
-        // the partners' last reads of this wavefront's area come before the
-        // staging of the stores below
-        __syncthreads();
-    } else {
-        // t < ntiles: block 0 of the request exists for lanes without a block
-        load_tile<D>(x, blk, v, lds[wv], lane);
-        lane_rounds<D, DIR>(v, tbl, tb.rounds);
-    }
+    float v[N];
+    // t < ntiles: block 0 of the request exists for lanes without a block
+    load_tile<D>(x, blk, v, lds[wv], lane);
+    lane_rounds<D, DIR>(v, tbl, tb.rounds);
     if (tb.modes[table]) {
-        const float* sg = tb.signs + table * N + q * V;
-        StaticFor<0, V>::run([&](auto ii) {
+        const float* sg = tb.signs + table * N;
+        StaticFor<0, N>::run([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             v[i] *= sg[i];
         });
     }
     if (bad) {
-        StaticFor<0, V>::run([&](auto ii) { v[decltype(ii)::value] = 0.0f; });
+        StaticFor<0, N>::run([&](auto ii) { v[decltype(ii)::value] = 0.0f; });
     }
     int lane2 = lane;
     asm volatile("" : "+v"(lane2));
@@ -1089,42 +1025,58 @@ __device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __
     int bb[CHP];
     instr_blocks<D>(bb, b, lane2);
     StaticFor<0, G::PARTS>::run([&](auto pp) {
-        store_part<D, decltype(pp)::value>(y + q * V, lds[wv], bb, v, lane2, sw2);
+        store_part<D, decltype(pp)::value>(y, lds[wv], bb, v, lane2, sw2);
     });
 }
 
-// Requests of N = 256: a wavefront per block, lane l holding elements
-// 4l .. 4l+3 (one 16-byte load and store per lane, 1 KB per wavefront). The
-// block's class is wave-uniform, so the multipliers of a pass are one
-// coalesced read of the class table: a pass along bit 0 or 1 pairs values
-// inside a lane (pairs 2l and 2l+1 of the pass, four floats); a pass along
-// bit K >= 2 pairs lane l with lane l ^ 2^(K-2), value by value, and lane l
-// reads the multipliers of pairs 4l' .. 4l'+3 (l' = l without bit K-2). Each
-// lane of such a pair fetches its partner's value and runs the pair's whole
-// lifting (bits < 6) or its own half of the (cos, sin) step (bits 6, 7) with
-// the same FMAs, operands and order as the grouped tiles, so results are
-// bit-identical to theirs; it keeps its own output. Lane-per-block tiles of
-// N = 256 take every multiplier as a per-lane 16-byte load from its block's
-// table and keep a request of 8192 blocks on 512 wavefronts; this layout
-// moves the same table bytes in whole rows and gives that request 8192
-// wavefronts. Multipliers are read one pass ahead.
-//
-// Multipliers of pass kk (application order) of round r for this lane: two
-// float4 (the first only, for passes along bits 0 and 1).
-template <int DIR>
-__device__ __forceinline__ void mult256(const float* tbl, int64_t r, int kk, int lane,
-                                        float4& m0, float4& m1) {
-    const int K = DIR == 0 ? kk : 7 - kk;
-    const float* pass = tbl + (r * 8 + kk) * 256;
-    if (K < 2) {
-        m0 = reinterpret_cast<const float4*>(pass)[lane];
-        m1 = m0;
+// Requests of N = 64, 128, 256: a wavefront per block, lane l holding the
+// V = N / 64 elements Vl .. Vl+V-1 (one 4-, 8- or 16-byte load and store per
+// lane, the whole block per wavefront). The block's class is wave-uniform,
+// so the multipliers of a pass are one coalesced read of the class table.
+// A pass along a bit below log2 V pairs values inside a lane (pairs
+// (V/2)l .. (V/2)l + V/2 - 1 of the pass); a pass along bit K >= log2 V
+// pairs lane l with lane l ^ 2^(K - log2 V), value by value, and lane l
+// reads the multipliers of pairs Vl' .. Vl'+V-1 (l' = l without that bit).
+// Each lane of such a pair fetches its partner's value and runs the pair's
+// whole lifting (bits < 6) or its own half of the (cos, sin) step (bits 6,
+// 7) with the same FMAs, operands and order as the grouped tiles, so results
+// are bit-identical to theirs; it keeps its own output. Lane-per-block tiles
+// read every multiplier as a per-lane load from the block's own table and
+// keep a request of 8192 blocks on 128 to 512 wavefronts; this layout moves
+// the same table bytes in whole rows, at 2-5x the arithmetic, and gives
+// that request 8192 wavefronts. Multipliers are read one pass ahead.
+
+// F consecutive floats (2, 4 or 8) from p, 8-byte aligned (16 for F >= 4).
+template <int F>
+__device__ __forceinline__ void load_floats(const float* p, float (&m)[8]) {
+    if constexpr (F == 2) {
+        const float2 a = *reinterpret_cast<const float2*>(p);
+        m[0] = a.x, m[1] = a.y;
     } else {
-        const int b = K - 2;
+        const float4 a = reinterpret_cast<const float4*>(p)[0];
+        m[0] = a.x, m[1] = a.y, m[2] = a.z, m[3] = a.w;
+        if constexpr (F == 8) {
+            const float4 b = reinterpret_cast<const float4*>(p)[1];
+            m[4] = b.x, m[5] = b.y, m[6] = b.z, m[7] = b.w;
+        }
+    }
+}
+
+// Multipliers of pass KK (application order) of round r for this lane.
+template <int D, int DIR, int KK>
+__device__ __forceinline__ void block_mult(const float* tbl, int64_t r, int lane,
+                                           float (&m)[8]) {
+    constexpr int N = 1 << D;
+    constexpr int V = N / 64;
+    constexpr int LB = D - kLaneBits;  // bits inside a lane
+    constexpr int K = DIR == 0 ? KK : D - 1 - KK;
+    const float* pass = tbl + (r * D + KK) * N;
+    if constexpr (K < LB) {
+        if constexpr (V >= 2) load_floats<V>(pass + V * lane, m);
+    } else {
+        constexpr int b = K - LB;
         const int lr = ((lane >> (b + 1)) << b) | (lane & ((1 << b) - 1));
-        const float4* q = reinterpret_cast<const float4*>(pass + 8 * lr);
-        m0 = q[0];
-        m1 = q[1];
+        load_floats<2 * V>(pass + 2 * V * lr, m);
     }
 }
 
@@ -1134,13 +1086,14 @@ __device__ __forceinline__ void lift_pair(float& a, float& b, float p, float q) 
     a = fmaf(p, b, a);
 }
 
-template <int DIR>
-__device__ __forceinline__ void request_block256(const ReqTable& tb, const float* __restrict__ x,
-                                                 float* __restrict__ y,
-                                                 const int32_t* __restrict__ cls,
-                                                 int64_t nblocks, int64_t lw, int wv, int lane,
-                                                 int32_t* status) {
-    constexpr int N = 256;
+template <int D, int DIR>
+__device__ __forceinline__ void request_block(const ReqTable& tb, const float* __restrict__ x,
+                                              float* __restrict__ y,
+                                              const int32_t* __restrict__ cls, int64_t nblocks,
+                                              int64_t lw, int wv, int lane, int32_t* status) {
+    constexpr int N = 1 << D;
+    constexpr int V = N / 64;
+    constexpr int LB = D - kLaneBits;
     const int64_t blk = lw * 4 + wv;
     if (blk >= nblocks) return;  // no barrier on this path
     int c = cls != nullptr ? __builtin_amdgcn_readfirstlane(cls[blk]) : 0;
@@ -1154,45 +1107,53 @@ __device__ __forceinline__ void request_block256(const ReqTable& tb, const float
         c = 0;
     }
     const size_t table = static_cast<size_t>(DIR) * tb.nclasses + c;
-    const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * 8 * N;
-    const float4 in = reinterpret_cast<const float4*>(x + blk * N)[lane];
-    float v[4] = {in.x, in.y, in.z, in.w};
-    float4 m0, m1;
-    mult256<DIR>(tbl, 0, 0, lane, m0, m1);
+    const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * D * N;
+    float v[V];
+    {
+        float in[8];
+        if constexpr (V == 1)
+            in[0] = x[blk * N + lane];
+        else
+            load_floats<V>(x + blk * N + V * lane, in);
+        StaticFor<0, V>::run([&](auto ii) { v[decltype(ii)::value] = in[decltype(ii)::value]; });
+    }
+    float m[8];
+    block_mult<D, DIR, 0>(tbl, 0, lane, m);
     for (int r = 0; r < tb.rounds; ++r) {
-        StaticFor<0, 8>::run([&](auto kk) {
+        StaticFor<0, D>::run([&](auto kk) {
             constexpr int k = decltype(kk)::value;
-            constexpr int K = DIR == 0 ? k : 7 - k;
-            const float4 a0 = m0, a1 = m1;
-            // the next pass's multipliers (past the last pass: the last again)
-            if (k + 1 < 8)
-                mult256<DIR>(tbl, r, k + 1, lane, m0, m1);
+            constexpr int K = DIR == 0 ? k : D - 1 - k;
+            float a[8];
+            StaticFor<0, 8>::run([&](auto ii) { a[decltype(ii)::value] = m[decltype(ii)::value]; });
+            // the next pass's multipliers (after the last pass: pass 0 of
+            // the next round, or of this one again)
+            if constexpr (k + 1 < D)
+                block_mult<D, DIR, k + 1>(tbl, r, lane, m);
             else
-                mult256<DIR>(tbl, r + 1 < tb.rounds ? r + 1 : r, r + 1 < tb.rounds ? 0 : 7,
-                             lane, m0, m1);
-            if constexpr (K == 0) {
-                lift_pair(v[0], v[1], a0.x, a0.y);
-                lift_pair(v[2], v[3], a0.z, a0.w);
-            } else if constexpr (K == 1) {
-                lift_pair(v[0], v[2], a0.x, a0.y);
-                lift_pair(v[1], v[3], a0.z, a0.w);
+                block_mult<D, DIR, 0>(tbl, r + 1 < tb.rounds ? r + 1 : r, lane, m);
+            if constexpr (K < LB) {
+                // pair t: values i and i + 2^K, i with bit K clear
+                StaticFor<0, V / 2>::run([&](auto tt) {
+                    constexpr int t = decltype(tt)::value;
+                    constexpr int i = ins0(t, K);
+                    lift_pair(v[i], v[i + (1 << K)], a[2 * t], a[2 * t + 1]);
+                });
             } else {
-                constexpr int mask = 1 << (K - 2);
+                constexpr int mask = 1 << (K - LB);
                 const bool hi = (lane & mask) != 0;
-                float w[4];
-                StaticFor<0, 4>::run([&](auto ii) {
+                float w[V];
+                StaticFor<0, V>::run([&](auto ii) {
                     constexpr int i = decltype(ii)::value;
                     w[i] = __shfl_xor(v[i], mask, 64);
                 });
-                const float mm[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-                StaticFor<0, 4>::run([&](auto ii) {
+                StaticFor<0, V>::run([&](auto ii) {
                     constexpr int i = decltype(ii)::value;
-                    const float p = mm[2 * i], q = mm[2 * i + 1];
+                    const float p = a[2 * i], q = a[2 * i + 1];
                     if constexpr (K < kLaneBits) {
-                        float a = hi ? w[i] : v[i];
-                        float b = hi ? v[i] : w[i];
-                        lift_pair(a, b, p, q);
-                        v[i] = hi ? b : a;
+                        float lo_v = hi ? w[i] : v[i];
+                        float hi_v = hi ? v[i] : w[i];
+                        lift_pair(lo_v, hi_v, p, q);
+                        v[i] = hi ? hi_v : lo_v;
                     } else {
                         // (cos, sin): y_m = c x_m + s x_n, y_n = c x_n - s x_m
                         const float sg = hi ? -q : q;
@@ -1203,14 +1164,23 @@ __device__ __forceinline__ void request_block256(const ReqTable& tb, const float
         });
     }
     if (tb.modes[table]) {
-        const float4 sg = reinterpret_cast<const float4*>(tb.signs + table * N)[lane];
-        v[0] *= sg.x;
-        v[1] *= sg.y;
-        v[2] *= sg.z;
-        v[3] *= sg.w;
+        const float* sg = tb.signs + table * N + V * lane;
+        StaticFor<0, V>::run([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            v[i] *= sg[i];
+        });
     }
-    if (bad) v[0] = v[1] = v[2] = v[3] = 0.0f;
-    store_nt(y + blk * N + 4 * lane, make_float4(v[0], v[1], v[2], v[3]));
+    if (bad) StaticFor<0, V>::run([&](auto ii) { v[decltype(ii)::value] = 0.0f; });
+    float* out = y + blk * N + V * lane;
+    if constexpr (V == 4) {
+        store_nt(out, make_float4(v[0], v[1], v[2], v[3]));
+    } else if constexpr (V == 2) {
+        typedef float vf2 __attribute__((ext_vector_type(2)));
+        const vf2 o = {v[0], v[1]};
+        __builtin_nontemporal_store(o, reinterpret_cast<vf2*>(out));
+    } else {
+        __builtin_nontemporal_store(v[0], out);
+    }
 }
 
 // The address u, of global memory, as a pointer that the compiler knows to
@@ -1269,16 +1239,21 @@ __device__ __forceinline__ ReqWork locate_request(const RequestArgs& a, int w) {
     return o;
 }
 
-// Requests of N = 256 (wavefront per block).
+// Requests of N >= 64 (a wavefront per block).
 template <int DIR>
 __global__ __launch_bounds__(256) void request_wide_kernel(RequestArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ReqWork o = locate_request(a, blockIdx.x);
-    request_block256<DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status);
+    switch (o.tb.log2n) {
+        case 6: request_block<6, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
+        case 7: request_block<7, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
+        case 8: request_block<8, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
+        default: break;
+    }
 }
 
-// Requests of N <= 128.
+// Requests of N <= 32.
 template <int DIR>
 __global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
     __shared__ float4 lds[4][512];
@@ -1297,8 +1272,6 @@ __global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
         case 3: request_tile<3, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 4: request_tile<4, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         case 5: request_tile<5, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 6: request_tile<6, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 7: request_tile<7, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
         default: break;
     }
 }

@@ -72,11 +72,13 @@ def test_served_results_match_oracle_and_alone():
     from paper_2505_21728_amd import serve
 
     tables, angles, pools = _workload(dev, 35, 6000, seed=80)
-    # small batches, so that requests queue and batches hold several of them
+    # small batches and more work offered than the device serves, so that
+    # requests queue, batches hold several of them, and a batch is often
+    # dispatched while the one before it still runs
     srv = serve.Server(tables, capacity={4: 3000, 6: 3000, 8: 3000}, slots=2, ring=64)
-    reqs = serve.make_requests(60, tables, pools, seed=7, min_blocks=16, max_blocks=2000)
+    reqs = serve.make_requests(60, tables, pools, seed=7, min_blocks=500, max_blocks=3000)
     torch.cuda.synchronize()
-    stats = serve.run_poisson(srv, reqs, rate=20000.0)
+    stats = serve.run_poisson(srv, reqs, rate=200000.0)
     _say(f"[gpu] serve: {stats}")
     assert stats["batches"] < len(reqs)                 # requests were batched together
     assert stats["overlapping_batches"] >= 2            # batches overlapped on the device
