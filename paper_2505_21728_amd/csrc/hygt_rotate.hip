@@ -28,8 +28,10 @@
 // row through a per-wavefront LDS row area after the passes (forward) or
 // before them (inverse). The fused launch for batches of several block
 // sizes (mixed_kernel) runs the same tile body over one persistent grid.
-// The request kernel (request_kernel, at the end) serves batches of requests
-// with no class grouping: its lanes follow their own classes' tables.
+// The request kernels (at the end) serve batches of requests with no class
+// grouping: for N <= 32 each lane follows its own block's class table, for
+// N >= 64 a wavefront takes one block and reads its class table a pass at a
+// time.
 //
 // Memory. The single-size kernels with N <= 64 bring a tile in through LDS
 // by DMA: each global_load_lds_dwordx4 reads the chunks of several whole
