@@ -31,6 +31,7 @@ alone, in any mix, or through hygt_plan + hygt_apply.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -275,29 +276,42 @@ def run_poisson(server: Server, requests: list, rate: float, seed: int = 4) -> d
 
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, len(requests))
-    t_start = time.perf_counter()
-    due = t_start + np.cumsum(gaps)
-    i = 0
-    while i < len(requests) or server.queue or any(s.busy for s in server.slots):
-        now = time.perf_counter()
-        while i < len(requests) and due[i] <= now:
-            requests[i].arrival = float(due[i])
-            server.submit(requests[i])
-            i += 1
-        server.poll()
+    # the server's counters before this run (it may have served others)
+    batches0, busy0 = server.batches, server.busy_s
+    log0, dispatch0 = len(server.batch_log), server.dispatch_s
+    # The collector stays off while requests are served: a collection of the
+    # older generations pauses the loop for up to milliseconds, which then
+    # shows as the latency of whatever arrived meanwhile.
+    collecting = gc.isenabled()
+    gc.disable()
+    try:
+        t_start = time.perf_counter()
+        due = t_start + np.cumsum(gaps)
+        i = 0
+        while i < len(requests) or server.queue or any(s.busy for s in server.slots):
+            now = time.perf_counter()
+            while i < len(requests) and due[i] <= now:
+                requests[i].arrival = float(due[i])
+                server.submit(requests[i])
+                i += 1
+            server.poll()
+    finally:
+        if collecting:
+            gc.enable()
     t_end = max(r.done for r in requests)
     lat = np.array([r.done - r.arrival for r in requests]) * 1e3
     blocks = sum(r.nblocks for r in requests)
-    busy = server.busy_s
+    busy = server.busy_s - busy0
+    batches = server.batches - batches0
     per_batch = collections.Counter(r.batch for r in requests)
-    return {"requests": len(requests), "blocks": blocks, "batches": server.batches,
+    return {"requests": len(requests), "blocks": blocks, "batches": batches,
             "max_requests_per_batch": max(per_batch.values()),
-            "overlapping_batches": overlapping_batches(server.batch_log),
+            "overlapping_batches": overlapping_batches(server.batch_log[log0:]),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
             "blocks_per_s": blocks / (t_end - t_start), "wall_s": t_end - t_start,
             "device_busy_s": busy, "offered_rate": rate,
-            "host_dispatch_us_per_batch": 1e6 * server.dispatch_s / max(server.batches, 1)}
+            "host_dispatch_us_per_batch": 1e6 * (server.dispatch_s - dispatch0) / max(batches, 1)}
 
 
 def overlapping_batches(log: list) -> int:
