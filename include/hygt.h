@@ -338,7 +338,7 @@ int hygt_mixed_graph_create(const hygt_segment* segs, int nseg, int direction, i
 int hygt_graph_launch(hygt_graph graph, hipStream_t stream);
 int hygt_graph_destroy(hygt_graph graph);
 
-/* ---- Request queue: batches of requests in one launch (serving) ---------
+/* ---- Request queue: single-launch batches of requests (serving) ---------
  *
  * For a serving loop that transforms requests as they arrive (a codec's
  * frames, Sec. VI: blocks of one size each, with a class per block), where
@@ -346,18 +346,16 @@ int hygt_graph_destroy(hygt_graph graph);
  * block size are built once (hygt_table_build()) and stay on the device. The
  * requests themselves are descriptors in a ring in pinned host memory that
  * the caller fills: one launch (hygt_requests_apply()) transforms a run of
- * consecutive ring entries (two launches when it mixes N = 256 with smaller
- * sizes), with no plan, no workspace and no class grouping.
+ * consecutive ring entries, with no plan, no workspace and no class grouping.
  * The call hands the run's descriptors to the launch with its arguments (so
  * that no wavefront reads host memory: such reads cost about 0.1 us each,
  * one after another, which for a launch of 512 workgroups took 1.3 ms), and
  * the device writes each request's status back into its ring entry.
- * For N <= 128 each lane takes one block and follows its own class's table
- * (the multipliers arrive by vector loads, not as wave-uniform scalars); for
- * N = 256 a wavefront takes one block, four values per lane, and reads its
- * class's table a pass at a time. Either way a block's arithmetic, and so
- * its result, is bit for bit that of hygt_apply() with a plan of the same
- * angles. Bulk batches are faster through hygt_plan() + hygt_apply(), whose
+ * A wavefront takes one block (N >= 64, N/64 values per lane) or 64/N
+ * consecutive blocks (N <= 32, a value per lane), and a block's lanes read
+ * its own class's table a pass at a time, exchanging values with lane
+ * shuffles. A block's arithmetic, and so its result, is bit for bit that of
+ * hygt_apply() with a plan of the same angles. Bulk batches are faster through hygt_plan() + hygt_apply(), whose
  * class-sorted tiles read each multiplier once per 64 blocks. */
 
 /* Bytes of the table of one block size (0 for invalid sizes). */
@@ -400,8 +398,7 @@ typedef struct hygt_request {
 
 /* Transforms requests ring[(first + i) % capacity], i = 0 .. count - 1
  * (1 <= count <= HYGT_MAX_BATCH_REQUESTS), forward or inverse, in one launch
- * on `stream`, or two when the batch holds requests of N = 256 beside
- * smaller ones (those run a wavefront per block, in a kernel of their own).
+ * on `stream`.
  *   ring    capacity entries in pinned host memory that the device can
  *           write (hipHostMalloc), 8-byte aligned; other memory is rejected
  *           with HYGT_EINVAL (hipHostGetDevicePointer gives the device's

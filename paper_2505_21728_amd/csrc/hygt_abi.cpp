@@ -575,28 +575,21 @@ int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int
     // The batch's descriptors go to the launch by value (the kernel reads
     // them from its argument segment); only the statuses are written back
     // into the ring by the device.
-    // Requests of N >= 64 go to a launch of their own (`wide`, a wavefront
-    // per block), the others keep their order in `a`; first_wg counts each
-    // launch's workgroups.
-    hygt::RequestArgs wide = a;
-    int64_t wgs = 0, wide_wgs = 0;
-    int na = 0, nw = 0;
+    int64_t wgs = 0;
     for (int i = 0; i < count; ++i) {
         hygt_request& e = ring[(first + i) % capacity];
-        const bool is_wide = tables[e.table].log2n >= hygt::kLaneBits;
-        int64_t& w = is_wide ? wide_wgs : wgs;
-        e.first_wg = w;
-        hygt::ReqDesc& q = is_wide ? wide.req[nw++] : a.req[na++];
+        e.first_wg = wgs;
+        hygt::ReqDesc& q = a.req[i];
         q.x = e.x;
         q.y = e.y;
         q.cls = e.cls;
         q.nblocks = static_cast<int32_t>(e.nblocks);
         q.table = e.table;
-        q.first_wg = static_cast<int32_t>(w);
+        q.first_wg = static_cast<int32_t>(wgs);
         q.entry = i;
-        w += hygt::request_workgroups(e.nblocks, tables[e.table].log2n);
+        wgs += hygt::request_workgroups(e.nblocks, tables[e.table].log2n);
     }
-    if (wgs == 0 && wide_wgs == 0) return HYGT_OK;
+    if (wgs == 0) return HYGT_OK;
     // The device's address of the ring; fails (and nothing is launched) for
     // memory that is not pinned, device-accessible host memory.
     void* dring = nullptr;
@@ -608,14 +601,9 @@ int hygt_requests_apply(hygt_request* ring, int64_t capacity, int64_t first, int
                                           offsetof(hygt_request, status));
     a.capacity = capacity;
     a.first = first;
-    a.count = na;
+    a.count = count;
     a.ntables = ntables;
-    wide.status = a.status;
-    wide.capacity = capacity;
-    wide.first = first;
-    wide.count = nw;
-    wide.ntables = ntables;
-    const hipError_t err = hygt::launch_requests(a, wgs, wide, wide_wgs, direction, stream);
+    const hipError_t err = hygt::launch_requests(a, wgs, direction, stream);
     return err == hipSuccess ? HYGT_OK : HYGT_ELAUNCH;
 }
 

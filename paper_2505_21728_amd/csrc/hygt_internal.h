@@ -316,18 +316,16 @@ struct RequestArgs {
 static_assert(sizeof(RequestArgs) <= 4096, "kernel arguments");
 
 // Workgroups (of four wavefronts) of a request of nblocks blocks of 2^log2n
-// values: four tiles of 64 blocks for N <= 32; for N >= 64 four blocks, a
-// wavefront each.
+// values: a wavefront takes one block for N >= 64 and 64 / N blocks for
+// N <= 32.
 inline int64_t request_workgroups(int64_t nblocks, int log2n) {
     if (log2n >= kLaneBits) return (nblocks + 3) / 4;
-    return ((nblocks + kTile - 1) / kTile + 3) / 4;
+    const int64_t per = 4 * (int64_t{64} >> log2n);  // blocks per workgroup
+    return (nblocks + per - 1) / per;
 }
 
-// Requests of N <= 32 (a) and of N >= 64 (wide: a wavefront per block) go
-// to two launches: each kernel then has the register budget of its own
-// paths only.
-hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, const RequestArgs& wide,
-                           int64_t wide_workgroups, int direction, hipStream_t stream);
+hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, int direction,
+                           hipStream_t stream);
 
 // Dense per-class transform (hygt_dense.hip), N = 64.
 hipError_t launch_dense(const float* x, float* y, int64_t nblocks, const unsigned short* mats,

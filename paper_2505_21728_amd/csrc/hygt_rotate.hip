@@ -28,10 +28,9 @@
 // row through a per-wavefront LDS row area after the passes (forward) or
 // before them (inverse). The fused launch for batches of several block
 // sizes (mixed_kernel) runs the same tile body over one persistent grid.
-// The request kernels (at the end) serve batches of requests with no class
-// grouping: for N <= 32 each lane follows its own block's class table, for
-// N >= 64 a wavefront takes one block and reads its class table a pass at a
-// time.
+// The request kernel (at the end) serves batches of requests with no class
+// grouping: a wavefront takes one block (or 64 / N blocks of N <= 32) and
+// reads its class table a pass at a time.
 //
 // Memory. The single-size kernels with N <= 64 bring a tile in through LDS
 // by DMA: each global_load_lds_dwordx4 reads the chunks of several whole
@@ -883,153 +882,11 @@ hipError_t launch_rotate(const float* x, float* y, int64_t nblocks, int log2n, i
 
 
 // ---------------------------------------------------------------------------
-// Request batches: one launch over a run of request descriptors, with a lane
-// per block that follows its own class's table
+// Request batches: one launch over a run of request descriptors, with no
+// class grouping: every block follows its own class's table
 // ---------------------------------------------------------------------------
 
 namespace {
-
-// A lane's own multiplier table, read with 16-byte vector loads P chunks
-// ahead of their use. The lanes of a wavefront hold blocks of different
-// classes here, so the multipliers cannot be wave-uniform scalars, and a
-// small batch has too few wavefronts to hide the loads' latency with each
-// other: the stream keeps P chunks in flight. next() passes the oldest chunk
-// to an empty asm statement that also rewrites the table address: the
-// compiler waits for that chunk there (while the younger ones stay in
-// flight), and the load issued next, addressed from the rewritten value,
-// cannot move above it.
-#ifndef HYGT_LANE_PREFETCH
-#define HYGT_LANE_PREFETCH 3
-#endif
-constexpr int kLanePrefetch = HYGT_LANE_PREFETCH;
-
-template <int F, int P = kLanePrefetch>
-struct LaneStream {
-    static_assert(F >= 4, "chunks of whole 16-byte loads");
-    static_assert(P >= 1, "chunks in flight");
-    uint64_t base;
-    Chunk<F> c[P];  // requested, oldest first
-    __device__ __forceinline__ void load(Chunk<F>& ch, int64_t off) {
-        constexpr int W = Chunk<F>::W;
-        // global (not generic) loads: they count only against vmcnt
-        typedef float vf4 __attribute__((ext_vector_type(4)));
-        typedef const __attribute__((address_space(1))) vf4* gptr;
-        const gptr p = reinterpret_cast<gptr>(base + static_cast<uint64_t>(off) * 4);
-        StaticFor<0, F / 4>::run([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            const vf4 f = p[k];
-            ch.a[(4 * k) / W][(4 * k) % W] = f.x;
-            ch.a[(4 * k + 1) / W][(4 * k + 1) % W] = f.y;
-            ch.a[(4 * k + 2) / W][(4 * k + 2) % W] = f.z;
-            ch.a[(4 * k + 3) / W][(4 * k + 3) % W] = f.w;
-        });
-    }
-    // Requests the first P chunks, at offset_of(i) for i = 0 .. P-1.
-    template <class OffsetOf>
-    __device__ __forceinline__ void begin(const float* table, OffsetOf&& offset_of) {
-        base = reinterpret_cast<uint64_t>(table);
-        StaticFor<0, P>::run([&](auto ii) { load(c[decltype(ii)::value], offset_of(ii)); });
-    }
-    // Returns the oldest requested chunk and requests the one at `off`.
-    __device__ __forceinline__ Chunk<F> next(int64_t off) {
-        if constexpr (Chunk<F>::NV == 1)
-            asm volatile("" : "+v"(base) : "v"(c[0].a[0]));
-        else
-            asm volatile("" : "+v"(base) : "v"(c[0].a[0]), "v"(c[0].a[1]));
-        const Chunk<F> got = c[0];
-        StaticFor<0, P - 1>::run([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            c[i] = c[i + 1];
-        });
-        load(c[P - 1], off);
-        return got;
-    }
-};
-
-// R rounds of D passes (N <= 64) with a lane's own table, which holds the
-// chunks in application order one after another.
-template <int D, int DIR>
-__device__ __forceinline__ void lane_rounds(float (&v)[1 << D], const float* tbl, int rounds) {
-    constexpr int N = 1 << D;
-    constexpr int F = chunk_floats<D>();
-    constexpr int CPP = N / F;
-    constexpr int CPR = D * CPP;
-    const int64_t last = static_cast<int64_t>(rounds) * CPR - 1;  // index of the last chunk
-    LaneStream<F> ls;
-    constexpr int P = kLanePrefetch;
-    ls.begin(tbl, [&](auto ii) -> int64_t {
-        constexpr int i = decltype(ii)::value;
-        return (i <= last ? i : last) * F;
-    });
-    for (int r = 0; r < rounds; ++r) {
-        StaticFor<0, CPR>::run([&](auto ee) {
-            constexpr int e = decltype(ee)::value;
-            constexpr int kk = e / CPP;
-            constexpr int H = e % CPP;
-            constexpr int K = DIR == 0 ? kk : D - 1 - kk;
-            const int64_t ahead = static_cast<int64_t>(r) * CPR + e + P;
-            const Chunk<F> m = ls.next((ahead <= last ? ahead : last) * F);
-            lift_chunk<D, K, H, F>(v, m);
-        });
-    }
-}
-
-// Local workgroup lw of a request of N = 2^D blocks, N <= 32: four tiles
-// of 64 consecutive blocks, a wavefront each. A lane loads its block's
-// class; one outside [0, nclasses) sets the request's status, runs with
-// class 0's table and writes zeros.
-template <int D, int DIR>
-__device__ __forceinline__ void request_tile(const ReqTable& tb, const float* __restrict__ x,
-                                             float* __restrict__ y,
-                                             const int32_t* __restrict__ cls, int64_t nblocks,
-                                             int64_t lw, int wv, int lane, float4 (*lds)[512],
-                                             int32_t* status) {
-    using G = TileGeo<D>;
-    static_assert(!G::SPLIT && D <= 5, "one lane per block");
-    constexpr int N = G::N;
-    constexpr int CHP = G::CHP;
-    const int64_t t = lw * 4 + wv;
-    const int64_t ntiles = (nblocks + kTile - 1) / kTile;
-    if (t >= ntiles) return;
-    const int64_t b64 = t * kTile + lane;
-    const int blk = b64 < nblocks ? static_cast<int>(b64) : -1;
-    int c = 0;
-    if (blk >= 0 && cls != nullptr) c = cls[blk];
-    const bool bad = blk >= 0 && (c < 0 || c >= tb.nclasses);
-    if (bad) {
-        // the ring is in host memory: a system-scope store, which no cache
-        // between the device and that memory holds back
-        __hip_atomic_store(status, static_cast<int32_t>(HYGT_ECLASS), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
-        c = 0;
-    }
-    const size_t table = static_cast<size_t>(DIR) * tb.nclasses + c;
-    const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * D * N;
-    float v[N];
-    // t < ntiles: block 0 of the request exists for lanes without a block
-    load_tile<D>(x, blk, v, lds[wv], lane);
-    lane_rounds<D, DIR>(v, tbl, tb.rounds);
-    if (tb.modes[table]) {
-        const float* sg = tb.signs + table * N;
-        StaticFor<0, N>::run([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            v[i] *= sg[i];
-        });
-    }
-    if (bad) {
-        StaticFor<0, N>::run([&](auto ii) { v[decltype(ii)::value] = 0.0f; });
-    }
-    int lane2 = lane;
-    asm volatile("" : "+v"(lane2));
-    const int sw2 = swz<CHP>(lane2);
-    int b = blk;
-    asm volatile("" : "+v"(b));
-    int bb[CHP];
-    instr_blocks<D>(bb, b, lane2);
-    StaticFor<0, G::PARTS>::run([&](auto pp) {
-        store_part<D, decltype(pp)::value>(y, lds[wv], bb, v, lane2, sw2);
-    });
-}
 
 // Requests of N = 64, 128, 256: a wavefront per block, lane l holding the
 // V = N / 64 elements Vl .. Vl+V-1 (one 4-, 8- or 16-byte load and store per
@@ -1185,6 +1042,66 @@ __device__ __forceinline__ void request_block(const ReqTable& tb, const float* _
     }
 }
 
+// Requests of N <= 32: a wavefront takes G = 64 / N consecutive blocks, lane
+// l element l mod N of block l / N, each group of N lanes with its block's
+// own class (so the multipliers are per-lane 8-byte loads, coalesced within
+// a group's table row). Every pass pairs lane l with lane l ^ 2^K inside its
+// group; both run the pair's lifting and keep their own output, as above.
+template <int D, int DIR>
+__device__ __forceinline__ void request_small(const ReqTable& tb, const float* __restrict__ x,
+                                              float* __restrict__ y,
+                                              const int32_t* __restrict__ cls, int64_t nblocks,
+                                              int64_t lw, int wv, int lane, int32_t* status) {
+    constexpr int N = 1 << D;
+    constexpr int G = 64 / N;
+    const int64_t blk0 = (lw * 4 + wv) * G;
+    if (blk0 >= nblocks) return;  // no barrier on this path
+    const int e = lane & (N - 1);
+    const int64_t blk = blk0 + (lane >> D);
+    const bool valid = blk < nblocks;
+    int c = 0;
+    if (valid && cls != nullptr) c = cls[blk];
+    const bool bad = valid && (c < 0 || c >= tb.nclasses);
+    if (bad) {
+        // the ring is in host memory: a system-scope store, which no cache
+        // between the device and that memory holds back
+        __hip_atomic_store(status, static_cast<int32_t>(HYGT_ECLASS), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        c = 0;
+    }
+    const size_t table = static_cast<size_t>(DIR) * tb.nclasses + c;
+    const float* tbl = tb.coef + table * static_cast<size_t>(tb.rounds) * D * N;
+    float v = valid ? x[blk * N + e] : 0.0f;
+    // multipliers of pass KK of round r: pair e without bit K
+    auto mult = [&](int64_t r, auto kkc) -> float2 {
+        constexpr int KK = decltype(kkc)::value;
+        constexpr int K = DIR == 0 ? KK : D - 1 - KK;
+        const int j = ((e >> (K + 1)) << K) | (e & ((1 << K) - 1));
+        return reinterpret_cast<const float2*>(tbl + (r * D + KK) * N)[j];
+    };
+    float2 m = mult(0, std::integral_constant<int, 0>{});
+    for (int r = 0; r < tb.rounds; ++r) {
+        StaticFor<0, D>::run([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            constexpr int K = DIR == 0 ? k : D - 1 - k;
+            const float2 a = m;
+            if constexpr (k + 1 < D)
+                m = mult(r, std::integral_constant<int, k + 1>{});
+            else
+                m = mult(r + 1 < tb.rounds ? r + 1 : r, std::integral_constant<int, 0>{});
+            const bool hi = (e >> K) & 1;
+            const float w = __shfl_xor(v, 1 << K, 64);
+            float lo_v = hi ? w : v;
+            float hi_v = hi ? v : w;
+            lift_pair(lo_v, hi_v, a.x, a.y);
+            v = hi ? hi_v : lo_v;
+        });
+    }
+    if (tb.modes[table]) v *= tb.signs[table * N + e];
+    if (bad) v = 0.0f;
+    if (valid) __builtin_nontemporal_store(v, y + blk * N + e);
+}
+
 // The address u, of global memory, as a pointer that the compiler knows to
 // be global (made from the integer as a global pointer, then converted), so
 // that every access derived from it is a global rather than a generic
@@ -1241,13 +1158,18 @@ __device__ __forceinline__ ReqWork locate_request(const RequestArgs& a, int w) {
     return o;
 }
 
-// Requests of N >= 64 (a wavefront per block).
+// A request batch: every size, a wavefront per block (N >= 64) or per
+// 64 / N blocks (N <= 32).
 template <int DIR>
-__global__ __launch_bounds__(256) void request_wide_kernel(RequestArgs a) {
+__global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ReqWork o = locate_request(a, blockIdx.x);
     switch (o.tb.log2n) {
+        case 2: request_small<2, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
+        case 3: request_small<3, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
+        case 4: request_small<4, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
+        case 5: request_small<5, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
         case 6: request_block<6, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
         case 7: request_block<7, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
         case 8: request_block<8, DIR>(o.tb, o.x, o.y, o.cls, o.nblocks, o.lw, wv, lane, o.status); break;
@@ -1255,51 +1177,17 @@ __global__ __launch_bounds__(256) void request_wide_kernel(RequestArgs a) {
     }
 }
 
-// Requests of N <= 32.
-template <int DIR>
-__global__ __launch_bounds__(256) void request_kernel(RequestArgs a) {
-    __shared__ float4 lds[4][512];
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const ReqWork o = locate_request(a, blockIdx.x);
-    const ReqTable& tb = o.tb;
-    const float* x = o.x;
-    float* y = o.y;
-    const int32_t* cls = o.cls;
-    const int64_t nblocks = o.nblocks;
-    const int64_t lw = o.lw;
-    int32_t* status = o.status;
-    switch (tb.log2n) {
-        case 2: request_tile<2, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 3: request_tile<3, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 4: request_tile<4, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        case 5: request_tile<5, DIR>(tb, x, y, cls, nblocks, lw, wv, lane, lds, status); break;
-        default: break;
-    }
-}
-
 }  // namespace
 
-hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, const RequestArgs& wide,
-                           int64_t wide_workgroups, int direction, hipStream_t stream) {
-    if (workgroups > 0) {
-        const dim3 grid(static_cast<unsigned>(workgroups));
-        if (direction == 0)
-            hipLaunchKernelGGL((request_kernel<0>), grid, dim3(256), 0, stream, a);
-        else
-            hipLaunchKernelGGL((request_kernel<1>), grid, dim3(256), 0, stream, a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (wide_workgroups > 0) {
-        const dim3 grid(static_cast<unsigned>(wide_workgroups));
-        if (direction == 0)
-            hipLaunchKernelGGL((request_wide_kernel<0>), grid, dim3(256), 0, stream, wide);
-        else
-            hipLaunchKernelGGL((request_wide_kernel<1>), grid, dim3(256), 0, stream, wide);
-        return hipGetLastError();
-    }
-    return hipSuccess;
+hipError_t launch_requests(const RequestArgs& a, int64_t workgroups, int direction,
+                           hipStream_t stream) {
+    if (workgroups <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>(workgroups));
+    if (direction == 0)
+        hipLaunchKernelGGL((request_kernel<0>), grid, dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((request_kernel<1>), grid, dim3(256), 0, stream, a);
+    return hipGetLastError();
 }
 
 }  // namespace hygt

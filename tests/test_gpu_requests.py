@@ -1,17 +1,15 @@
 """The request path (hygt_table_build + hygt_requests_apply, Sec. IV eq. (5),
 (6), (9)) through the C ABI with device data, against the FP64 oracle.
 
-One call transforms a run of ring entries of different block sizes (N = 4
-to 256; the requests of N = 256 in a second launch of their own, a
-wavefront per block), ragged block counts (1, 63, 64, 65, ...) and an
-empty request; the
+One launch transforms a run of ring entries of different block sizes (N = 4
+to 256), ragged block counts (1, 63, 64, 65, ...) and an empty request; the
 ring wraps around (the run starts near its end); one request runs in place
 and one has a single class with cls = NULL. Each output matches the oracle
 (relative L2 <= 1e-5 per block and over the request, on sampled blocks) and,
 bit for bit, hygt_plan + hygt_apply on the same blocks, in both directions.
 A request with class indices out of range gets HYGT_ECLASS in its ring
-entry and zeros in those blocks, in either launch; the other requests of
-the call are not affected."""
+entry and zeros in those blocks; the other requests of its launch are not
+affected."""
 
 import sys
 
@@ -162,8 +160,9 @@ def test_requests_match_oracle_and_plan(launch):
 
 
 def test_request_with_bad_classes_is_flagged_and_zeroed():
-    """Bad classes in a request of N = 16 and in one of N = 256 (which runs
-    in the batch's second launch): each flags its own ring entry."""
+    """Bad classes in a request of N = 16 (several blocks per wavefront) and
+    in one of N = 256 (a wavefront per block): each flags its own ring
+    entry."""
     dev = _dev()
     specs = [(6, 4, 35), (4, 2, 7), (8, 2, 5)]
     tabs = _tables(specs, dev, seed=900)
