@@ -81,7 +81,7 @@ def _run(x, cls, ang, dev):
             ga_ref, mass)
 
 
-def test_backward_config4_small():
+def test_backward_8x8_8191_blocks():
     """8x8 AR(1) blocks, 35 classes, R = 4, 8191 blocks (ragged tiles).
 
     dL/dangles: each term g_m y_n - g_n y_m carries a few FP32 rounding errors
@@ -95,7 +95,7 @@ def test_backward_config4_small():
     ang = synth.angles(35, 4, 6)
     x = synth.ar1_blocks(8191, 8, seed=31)
     cls = synth.classes(8191, 35, seed=32)
-    _check_grads(*_run(x, cls, ang, dev), cls, 35, "backward cfg4-small")
+    _check_grads(*_run(x, cls, ang, dev), cls, 35, "backward 8x8 8191 blocks")
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])

@@ -54,7 +54,7 @@ def _close(got, ref, what):
     return eb.max()
 
 
-def test_dense_matches_oracle_cfg2_small():
+def test_dense_matches_oracle_8x8_8191_blocks():
     """8191 AR(1) 8x8 blocks, 35 classes: y = M_c x, then the transposed
     matrices applied to y; and the dense form tracks HyGT to BF16 accuracy."""
     dev = _dev()
@@ -65,7 +65,7 @@ def test_dense_matches_oracle_cfg2_small():
     cls = synth.classes(nb, C)
     m = _mats(ang)
     mt = np.ascontiguousarray(np.transpose(m, (0, 2, 1)))
-    _say(f"[gpu] dense cfg2-small B={nb} C={C}")
+    _say(f"[gpu] dense 8x8 B={nb} C={C}")
     plan = hygt.Plan(_to(ang, dev), _to(cls, dev))
     xt = _to(x, dev)
     y = plan.dense(xt, _mats_dev(m, dev))

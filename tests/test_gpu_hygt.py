@@ -74,23 +74,23 @@ def _parity(x, cls, ang, dev, what, use_cls=True):
     _assert_close(z, x.astype(np.float64), what + " inverse(forward(x)) vs x")
 
 
-def test_config1_n16_parity():
+def test_4x4_one_class_parity():
     """4x4 blocks: N=16, R=2, one class, 4096 Gaussian blocks (sigma 32)."""
     dev = _dev()
     ang = synth.angles(1, 2, 4)
     x = synth.gaussian_blocks(4096, 16)
     cls = np.zeros(4096, dtype=np.int32)
-    _parity(x, cls, ang, dev, "cfg1 with cls")
-    _parity(x, cls, ang, dev, "cfg1 cls=None", use_cls=False)
+    _parity(x, cls, ang, dev, "4x4 with cls")
+    _parity(x, cls, ang, dev, "4x4 cls=None", use_cls=False)
 
 
-def test_config2_small_parity():
+def test_8x8_8191_blocks_parity():
     """8x8 blocks: N=64, R=4, 35 classes, AR(1) residuals, ragged class tiles."""
     dev = _dev()
     ang = synth.angles(35, 4, 6)
     x = synth.ar1_blocks(8191, 8)
     cls = synth.classes(8191, 35)
-    _parity(x, cls, ang, dev, "cfg2-small")
+    _parity(x, cls, ang, dev, "8x8 8191 blocks")
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
@@ -248,14 +248,14 @@ def test_empty_batch():
     assert y.shape == (0, 16)
 
 
-def test_config2_full_size_sampled():
+def test_8x8_2p20_blocks_sampled():
     """2^20 8x8 blocks, 35 classes, R=4 in the benchmark's launch
     configuration; 2048 sampled blocks checked against the oracle, and the
     round trip checked on every block."""
     dev = _dev()
     hygt = _hygt()
     nb = 1 << 20
-    _say("[gpu] cfg2 full size: generating inputs")
+    _say("[gpu] 2^20 8x8 blocks: generating inputs")
     ang = synth.angles(35, 4, 6)
     x = synth.ar1_blocks(nb, 8)
     cls = synth.classes(nb, 35)
@@ -265,10 +265,10 @@ def test_config2_full_size_sampled():
     z = plan.inverse(y)
     torch.cuda.synchronize()
     plan.check()
-    _say("[gpu] cfg2 full size: comparing")
+    _say("[gpu] 2^20 8x8 blocks: comparing")
     sample = np.random.default_rng(21).choice(nb, 2048, replace=False)
     ys = y[torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
-    _assert_close(ys, orc.forward(x[sample], cls[sample], ang), "cfg2 full forward (sample)")
+    _assert_close(ys, orc.forward(x[sample], cls[sample], ang), "2^20 8x8 forward (sample)")
     # round trip on all blocks (relative L2, computed on the device in FP64)
     num = (z.double() - xt.double()).pow(2).sum(1).sqrt()
     den = xt.double().pow(2).sum(1).sqrt()

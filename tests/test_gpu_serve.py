@@ -1,4 +1,4 @@
-"""GPU tests of the continuous-batching server (the config-5 serving mix:
+"""GPU tests of the continuous-batching server (the serving mix:
 4x4 / 8x8 / 16x16 requests of separable AR(1) blocks with rho uniform in
 [0.7, 0.95], 35 classes per size).
 
