@@ -170,7 +170,10 @@ class Server:
         and writes its descriptor into the ring. Its x and cls must be complete
         on the device, or req.ready must be an event recorded after the work
         that writes them (the batch's stream then waits for it). The server
-        keeps the request, and so its tensors, until its batch has finished."""
+        keeps the request, and so its tensors, until its batch has finished.
+        An output given with the request keeps allocation off the serving
+        path (an allocation of a new size reaches the device allocator, which
+        can take longer than the transform)."""
         torch = _torch()
         d = req.log2n
         if d not in self._tindex:
