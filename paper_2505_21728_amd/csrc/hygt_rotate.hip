@@ -79,6 +79,10 @@ namespace {
 
 using namespace tile;
 
+// Chunks of multipliers in flight per wavefront with the VGPR stream
+// (VTableStream): the split tiles, and the 8x8 tiles of the mixed launch.
+constexpr int kStreamPrefetch = 4;
+
 // Floats of a multiplier chunk for pairs of N = 2^D values: the whole pass
 // for N < 32, else 16 pairs.
 template <int D>
@@ -165,12 +169,48 @@ __device__ __forceinline__ void int_chunk(float (&v)[1 << D], const Chunk<F>& m,
 // compile time (RT == R); RT == 0 loops over `rounds`. INTG selects the
 // integer butterflies. The prefetch after the last chunk of the last round
 // repeats that round's first chunk.
-template <int D, int DIR, int RT, bool INTG>
+//
+// With VS (N = 64 in the fused mixed launch only) the chunks come through the
+// VGPR stream of the split tiles instead (VTableStream, kStreamPrefetch
+// chunks in flight): the fused launch's 8x8 tiles share the GPU with
+// latency-bound 16x16 tiles, and there this took the mixed step from 88 to
+// 84.5 us, while the single-size 8x8 kernels lost 2 to 14 us with it.
+template <int D, int DIR, int RT, bool INTG, bool VS = false>
 __device__ __forceinline__ void run_rounds(float (&v)[1 << D], ctab_f tbl, int rounds) {
     constexpr int N = 1 << D;
     constexpr int F = chunk_floats<D>();
     constexpr int CPP = N / F;    // chunks per pass
     constexpr int CPR = D * CPP;  // chunks per round
+    if constexpr (VS) {
+        static_assert(F == 32 && !INTG, "chunks of 16 pairs");
+        constexpr int Q = kStreamPrefetch;
+        VTableStream<Q> vs;
+        vs.init(reinterpret_cast<uint64_t>(tbl), __lane_id());
+        // chunk g of the walk (past the last round: a chunk of the last one)
+        StaticFor<0, Q>::run([&](auto gg) {
+            constexpr int g = decltype(gg)::value;
+            const int64_t r2 = g / CPR < rounds ? g / CPR : rounds - 1;
+            vs.push(r2 * (D * N) + (g % CPR) * F);
+        });
+        auto one_round_v = [&](int64_t r) {
+            StaticFor<0, CPR>::run([&](auto ee) {
+                constexpr int e = decltype(ee)::value;
+                constexpr int kk = e / CPP;
+                constexpr int H = e % CPP;
+                constexpr int K = DIR == 0 ? kk : D - 1 - kk;
+                int64_t r2 = r + (e + Q) / CPR;
+                if (r2 > rounds - 1) r2 = rounds - 1;
+                const VChunk m = vs.next(r2 * (D * N) + ((e + Q) % CPR) * F);
+                lift_chunk<D, K, H, F>(v, m);
+            });
+        };
+        if constexpr (RT > 0) {
+            StaticFor<0, RT>::run([&](auto rr) { one_round_v(decltype(rr)::value); });
+        } else {
+            for (int r = 0; r < rounds; ++r) one_round_v(r);
+        }
+        return;
+    }
     int half = 0;
     if constexpr (INTG) {
         // the rounding constant, once in a VGPR (an instruction may read only
@@ -319,10 +359,8 @@ constexpr int split_chunk_pass(int j) {
     return kk;
 }
 
-// Chunks of multipliers in flight per wavefront of a split tile.
-constexpr int kSplitPrefetch = 4;
 
-template <int D, int DIR, int Q = kSplitPrefetch>
+template <int D, int DIR, int Q = kStreamPrefetch>
 __device__ __forceinline__ void run_passes_split(float (&v)[64], ctab_f tbl, ctab_f sign,
                                                  int has_neg, int rounds, int q, float4* area0,
                                                  int lane) {
@@ -439,7 +477,8 @@ __device__ __forceinline__ void unpermute_row(float* v, float4* R, ctab_i perm, 
 // completed, and no other wavefront touches it, so the restrict qualifiers
 // (which let the per-tile class loads stay scalar) hold for every pair of
 // accesses that the compiler could reorder.
-template <int D, int DIR, int RT, bool PERM = false, bool INTG = false, bool TILE_LOAD = false>
+template <int D, int DIR, int RT, bool PERM = false, bool INTG = false, bool TILE_LOAD = false,
+          bool VS = false>
 __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* __restrict__ y,
                                             int64_t nblocks, int rounds, int nclasses,
                                             int64_t t0, int c, int q,
@@ -480,7 +519,7 @@ __device__ __forceinline__ void rotate_tile(const float* __restrict__ x, float* 
     } else if constexpr (INTG) {
         run_rounds<D, DIR, 0, true>(v, tbl, rounds);
     } else {
-        run_rounds<D, DIR, RT, false>(v, tbl, rounds);
+        run_rounds<D, DIR, RT, false, VS && D == kLaneBits>(v, tbl, rounds);
         apply_signs<N>(v, as_ctab(signs) + table * N, as_ctab(modes)[table]);
         if constexpr (PERM && DIR == 0) permute_row<D>(v, L, outperm + c * N, lane);
     }
@@ -689,17 +728,17 @@ __device__ __forceinline__ void mixed_item(const MixedSeg& g, int64_t local, int
         if constexpr (UNROLL && D <= 6) {
             switch (g.rounds) {
                 case 1:
-                    rotate_tile<D, DIR, 1>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
+                    rotate_tile<D, DIR, 1, false, false, false, true>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
                                            g.perm, g.modes, g.coef, g.signs, lds[wv], lds[wv],
                                            lane);
                     return;
                 case 2:
-                    rotate_tile<D, DIR, 2>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
+                    rotate_tile<D, DIR, 2, false, false, false, true>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
                                            g.perm, g.modes, g.coef, g.signs, lds[wv], lds[wv],
                                            lane);
                     return;
                 case 4:
-                    rotate_tile<D, DIR, 4>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
+                    rotate_tile<D, DIR, 4, false, false, false, true>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0,
                                            g.perm, g.modes, g.coef, g.signs, lds[wv], lds[wv],
                                            lane);
                     return;
@@ -707,8 +746,10 @@ __device__ __forceinline__ void mixed_item(const MixedSeg& g, int64_t local, int
                     break;
             }
         }
-        rotate_tile<D, DIR, 0>(g.x, g.y, g.nblocks, g.rounds, g.nclasses, t0, c, 0, g.perm,
-                               g.modes, g.coef, g.signs, lds[wv], lds[wv], lane);
+        rotate_tile<D, DIR, 0, false, false, false, true>(g.x, g.y, g.nblocks, g.rounds,
+                                                          g.nclasses, t0, c, 0, g.perm, g.modes,
+                                                          g.coef, g.signs, lds[wv], lds[wv],
+                                                          lane);
     }
 }
 
