@@ -19,10 +19,11 @@
 // the pass before. Measured on MI355X (2^20 8x8 blocks, R = 4), this took
 // the forward transform from 119 to 112 us with the tiles in class order, and
 // made the cost of switching class tables between neighbouring tiles
-// negligible. Tiles of N >= 128 stream their chunks into VGPRs instead, four
-// chunks ahead, and read each multiplier from its lane of the row by DPP
-// (VTableStream in hygt_tile.h): their few wavefronts cannot hide a scalar
-// load's L2 round trip behind each other.
+// negligible. Tiles of N >= 128 (and the 8x8 tiles of the mixed launch)
+// stream their chunks into VGPRs instead, four chunks ahead, and read each
+// multiplier from its lane of the row by DPP (VTableStream in hygt_tile.h):
+// their few wavefronts cannot hide a scalar load's L2 round trip behind each
+// other.
 //
 // Variants. The permutation pass of Fig. 4 (N <= 64) reorders each lane's
 // row through a per-wavefront LDS row area after the passes (forward) or
